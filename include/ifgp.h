@@ -1,0 +1,232 @@
+/*
+ * ifgp.h -- C ABI of libifgp, InfraredGP's training-free feed-forward
+ * propagation (FFP) on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Qin, Li, Cui & Pei, "InfraredGP: Efficient Graph
+ * Partitioning via Spectral Graph Neural Networks with Negative Corrections",
+ * arXiv 2508.19737):
+ *
+ *   A        symmetric 0/1 adjacency of an undirected, unweighted graph
+ *            (Sec. II, problem statement)
+ *   D_tau    degree correction: Eq. (1) for tau <= 0, D + tau I for tau > 0
+ *            (Sec. I)
+ *   Z^(0)    N x d random input with entries ~ N(0, 1/d) (Sec. III-A, before
+ *            Eq. (4); Algorithm 1, noise step)
+ *   hop      phi * Z = theta Z + alpha D_tau^{-1/2} A D_tau^{-1/2} Z
+ *            (Eq. (3); Eq. (2) gives the general (alpha, theta) form)
+ *   layer    Z^(l) = ZNorm(tanh(phi * Z^(l-1))), ZNorm = column z-score
+ *            (Eq. (4))
+ *   output   Z~ = sigma(Z^(K)) (Eq. (4); Algorithm 1 up to the clustering
+ *            step, which is not part of this library)
+ *
+ * K is the number of hops (the paper's number of GNN layers L).
+ *
+ * Conventions for every call:
+ *   - Functions return ifgp_status; nothing aborts and no C++ exception
+ *     crosses this boundary.  On a non-OK status ifgp_last_error() gives a
+ *     message (per calling thread).
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  All device work is enqueued on the
+ *     `hip_stream` argument (NULL = the legacy default stream) and is complete
+ *     once that stream is synchronised; calls that must learn a size (graph
+ *     build, stream_add, export) synchronise it themselves.
+ *   - A graph handle owns all device memory it allocated (through the
+ *     allocator hook, see ifgp_set_allocator).  A handle is not thread-safe;
+ *     distinct handles may be used from distinct threads.
+ *   - Node ids are 0 .. N-1 and N must be below 2^31 - 1.
+ */
+#ifndef IFGP_H
+#define IFGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define IFGP_API __attribute__((visibility("default")))
+#else
+#define IFGP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifgp_graph_s *ifgp_graph_t;
+
+typedef enum {
+    IFGP_OK = 0,
+    IFGP_E_INVALID = -1, /* bad argument (size, pointer, dtype, parameter) */
+    IFGP_E_RANGE = -2,   /* a node id outside [0, N) */
+    IFGP_E_OOM = -3,     /* the allocator returned NULL */
+    IFGP_E_DEVICE = -4,  /* a HIP runtime call failed */
+    IFGP_E_STATE = -5    /* call not valid in the handle's current state */
+} ifgp_status;
+
+typedef enum {
+    IFGP_F32 = 0,  /* float32 */
+    IFGP_BF16 = 1, /* bfloat16 (storage only) */
+    IFGP_F16 = 2,  /* IEEE half (storage only) */
+    IFGP_F64 = 3   /* float64 (only ifgp_gaussian_input accepts it) */
+} ifgp_dtype;
+
+/*
+ * Filter and normalisation parameters.
+ *   alpha, theta  filter of Eq. (2)/(3); InfraredGP uses (1, 0.1) (Sec. III-A)
+ *   eps           the small positive value of Eq. (1); 0.001 in the paper
+ *   znorm_ddof    ZNorm standard deviation divisor N - ddof (0 or 1); 0 is the
+ *                 plain standard deviation of the column entries (Eq. (4))
+ *   storage       ifgp_dtype in which node features are kept in HBM between
+ *                 hops (F32, BF16 or F16); accumulation is always FP32 and the
+ *                 D_tau scales are always computed in FP64
+ */
+typedef struct {
+    double alpha;
+    double theta;
+    double eps;
+    int32_t znorm_ddof;
+    int32_t storage;
+} ifgp_params;
+
+/* Fill *p with the paper's settings: alpha 1, theta 0.1, eps 0.001, ddof 0,
+ * storage FP32.  Returns IFGP_E_INVALID if p is NULL. */
+IFGP_API ifgp_status ifgp_default_params(ifgp_params *p);
+
+/*
+ * Build a graph handle from an edge list (Sec. II: undirected, unweighted;
+ * Algorithm 1 input (V, E)).
+ *   src, dst        num_edges node ids each (int64), host memory if
+ *                   edges_on_device == 0, device memory otherwise; copied, so
+ *                   the caller may free them on return
+ *   N               number of nodes, 1 <= N < 2^31 - 1
+ *   out             receives the new handle (unchanged on error)
+ * Every pair is an undirected edge: (u, v) and (v, u) are the same edge, a pair
+ * listed more than once is one edge, and u == v is dropped (A in {0,1}, simple
+ * graph); both are counted (ifgp_graph_info).  The graph is kept in HBM as a
+ * CSR with strictly ascending column indices per row.
+ * Errors: IFGP_E_INVALID (N out of range, num_edges < 0, NULL pointers),
+ * IFGP_E_RANGE (an id outside [0, N); no handle is created), IFGP_E_OOM,
+ * IFGP_E_DEVICE.  Synchronises hip_stream.
+ */
+IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, int64_t num_edges,
+                             int64_t N, int edges_on_device, void *hip_stream,
+                             ifgp_graph_t *out);
+
+/*
+ * One FFP (Algorithm 1 from the D_tau step to the final sigmoid).
+ *   tau     degree correction; tau <= 0 uses Eq. (1), tau > 0 uses D + tau I
+ *   K       number of hops, K >= 0 (K = 0 returns sigma(Z^(0)))
+ *   d       embedding dimension, 1 <= d <= 256
+ *   seed    Z^(0)[i, c] is a pure function of (seed, i, c): Philox4x64-10
+ *           (Salmon et al., SC'11) with key (seed, 0) and counter
+ *           (i + 1, c, 0, 0), Box-Muller on output words 0 and 1 mapped to
+ *           ((w >> 11) + 0.5) 2^-53, scaled by d^{-1/2}
+ *   p       parameters, NULL = ifgp_default_params
+ *   out     device, N x d FP32, row-major, caller-owned; row i is node i
+ * Errors: IFGP_E_INVALID (d, K, tau not finite, params), IFGP_E_OOM,
+ * IFGP_E_DEVICE.  Does not synchronise.
+ */
+IFGP_API ifgp_status ifgp_embed(ifgp_graph_t g, double tau, int32_t K, int32_t d, uint64_t seed,
+                       const ifgp_params *p, float *out, void *hip_stream);
+
+/* As ifgp_embed with a caller-supplied Z^(0): X is device FP32 N x d
+ * row-major (row i is node i).  It is read before the call's first hop. */
+IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t d, const float *X,
+                         const ifgp_params *p, float *out, void *hip_stream);
+
+/*
+ * The random input alone: out[i, c] = Z^(0)[i, c] for 0 <= i < N, 0 <= c < d,
+ * by the rule given at ifgp_embed, rounded once to `dtype` (F64, F32, BF16 or
+ * F16).  out is device memory, N x d row-major.  Errors: IFGP_E_INVALID.
+ */
+IFGP_API ifgp_status ifgp_gaussian_input(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
+                                void *hip_stream);
+
+/*
+ * Merge an edge increment into the graph (Algorithm 2, topology merge and
+ * D_tau update).  new_N >= the current N; new_N == N is the emerging-edge
+ * model (nodes fixed), new_N > N adds isolated nodes N .. new_N - 1 before the
+ * increment's edges are merged.  Edge semantics as ifgp_build_graph.  After
+ * the call the graph equals ifgp_build_graph of the union of all edges so far.
+ * Strong guarantee: on any error the graph is unchanged.
+ * Errors: IFGP_E_INVALID, IFGP_E_RANGE, IFGP_E_OOM, IFGP_E_DEVICE.
+ * Synchronises hip_stream.
+ */
+IFGP_API ifgp_status ifgp_stream_add(ifgp_graph_t g, const int64_t *src, const int64_t *dst,
+                            int64_t num_edges, int64_t new_N, int edges_on_device,
+                            void *hip_stream);
+
+/*
+ * Embed several graphs together: every hop of every graph runs in one
+ * launch per (storage, padded width) class, so small graphs share the device.
+ * Arrays have n entries; outs[k] is graph k's device N_k x d_k FP32 output.
+ * The result for each graph is identical to ifgp_embed on that graph alone.
+ * A handle may appear at most once.  Errors as ifgp_embed.
+ */
+IFGP_API ifgp_status ifgp_embed_batch(ifgp_graph_t *gs, int32_t n, const double *tau, const int32_t *K,
+                             const int32_t *d, const uint64_t *seed, const ifgp_params *p,
+                             float **outs, void *hip_stream);
+
+/*
+ * Stepwise embedding, for serving loops that admit graphs between hops.
+ * ifgp_job_begin prepares Z^(0) of graph g (arguments as ifgp_embed) and
+ * sets its hop counter to 0; ifgp_job_step advances every listed graph with
+ * an unfinished job by one hop, batched as in ifgp_embed_batch, and writes
+ * the output of each job that reaches its K; *done_flags (host, n entries,
+ * may be NULL) receives 1 for jobs finished by this call or earlier.
+ * A job's result equals ifgp_embed with the same arguments.
+ * Errors: IFGP_E_STATE (ifgp_job_step on a handle without a job), others as
+ * ifgp_embed.
+ */
+IFGP_API ifgp_status ifgp_job_begin(ifgp_graph_t g, double tau, int32_t K, int32_t d, uint64_t seed,
+                           const ifgp_params *p, float *out, void *hip_stream);
+IFGP_API ifgp_status ifgp_job_step(ifgp_graph_t *gs, int32_t n, int32_t *done_flags, void *hip_stream);
+
+/* Sizes and counters: any output pointer may be NULL. */
+IFGP_API ifgp_status ifgp_graph_info(ifgp_graph_t g, int64_t *N, int64_t *nnz,
+                            int64_t *self_loops_dropped, int64_t *dups_dropped);
+
+/* Copy the CSR to host memory: rowptr N+1 entries, colidx nnz entries (ascending
+ * within each row), deg N entries.  Synchronises the stream of the last call. */
+IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *colidx, int32_t *deg);
+
+/* Copy s_i = (D_tau)_ii^{-1/2} in FP64 for node i = 0 .. N-1 to host memory
+ * (Eq. (1) / D + tau I, then the inverse square root). */
+IFGP_API ifgp_status ifgp_export_scales(ifgp_graph_t g, double tau, double eps, double *s_host);
+
+/* Device bytes a graph with N nodes and nnz stored entries needs resident for
+ * embeddings of width d in `storage` (graph, scales, features, statistics). */
+IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int32_t storage,
+                                 int64_t *bytes);
+
+/*
+ * Route every device allocation of the library through alloc/free (both
+ * non-NULL), or back to hipMalloc/hipFree (both NULL).  alloc(bytes, stream,
+ * ctx) returns device memory usable on `stream` or NULL; free(ptr, stream,
+ * ctx) releases it.  Process-wide; set it before creating handles and keep the
+ * callbacks alive while any handle exists.
+ */
+IFGP_API ifgp_status ifgp_set_allocator(void *(*alloc)(size_t, void *, void *),
+                               void (*free_fn)(void *, void *, void *), void *ctx);
+
+/*
+ * Kernel timing: while enabled on a handle, each hop launch of that handle is
+ * bracketed by HIP events on its stream.  ifgp_timing_read synchronises those
+ * events and returns the number of hop launches and their summed duration in
+ * milliseconds since the last read, then clears them.
+ */
+IFGP_API ifgp_status ifgp_timing_enable(ifgp_graph_t g, int enable);
+IFGP_API ifgp_status ifgp_timing_read(ifgp_graph_t g, int64_t *hop_launches, double *hop_ms);
+
+/* Release the handle and all its device memory (NULL is accepted). */
+IFGP_API ifgp_status ifgp_destroy(ifgp_graph_t g);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+IFGP_API const char *ifgp_last_error(void);
+
+/* Library version string. */
+IFGP_API const char *ifgp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFGP_H */

@@ -1,0 +1,838 @@
+// InfraredGP's feed-forward propagation on gfx950.
+//
+// Layer l (Eq. (4)) with the filter of Eq. (3):
+//     Y = theta Zn + alpha S A S Zn,   T = tanh(Y),   Z^(l) = ZNorm(T)
+// where S = D_tau^{-1/2} (Eq. (1)) and Zn = Z^(l-1).
+//
+// Storage between hops.  Row i of the feature buffer holds W_i = s_i T_i
+// (s_i = (D_tau)_ii^{-1/2}) rounded to the storage type, and ZNorm is applied
+// lazily by the next hop through per-column a_c = 1/sigma_c, b_c = -mu_c/sigma_c
+// (Zn = a T + b).  Then
+//     sum_j s_j Zn_j = a (sum_j W_j) + b r_i,     r_i = sum_{j in N(i)} s_j,
+// so a hop gathers W rows and adds them, with no per-neighbour multiply and no
+// per-neighbour scale load; the self term uses T_i = W_i sqrt((D_tau)_ii).
+// Z^(0) is stored the same way (W = s X) with a = 1, b = 0.
+//
+// Column statistics (mu, sigma of T, Eq. (4)) are gathered in FP64 from the
+// values actually stored, per block, then reduced in a fixed order by a
+// finalize kernel: results are deterministic run to run.
+//
+// Kernel geometry (wave64): a row of D storage elements is read as 16-byte
+// vectors by LPR = D / (16 / sizeof(T)) lanes.  Rows are in descending-degree
+// order (plan built with the graph), split into three classes:
+//   hub     deg >= 4096  one 256-thread block per row
+//   medium  deg >= 256   one wave per row (subgroups split the neighbours)
+//   light   the rest     one LPR-lane subgroup per row, 256 rows per block
+// Heavy rows come first in the grid, so long blocks start early.
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace ifgp {
+namespace {
+
+constexpr int THREADS = 256;
+constexpr int WAVES = THREADS / 64;
+constexpr int U = 8;   // neighbour rows in flight per lane
+
+template <typename T, int D> struct Cfg {
+    static constexpr int EPL = 16 / (int)sizeof(T);   // elements per lane
+    static constexpr int LPR = D / EPL;               // lanes per row
+    static constexpr int RPW = 64 / LPR;              // rows (subgroups) per wave
+    static constexpr int QI = (U + LPR - 1) / LPR;    // index loads per lane per chunk
+    static_assert(LPR >= 1 && LPR <= 64 && (64 % LPR) == 0, "unsupported width");
+    static_assert(LIGHT_ROWS_PER_BLOCK % (WAVES * RPW) == 0, "light block shape");
+};
+
+// ---------------------------------------------------------------- pack/unpack
+__device__ __forceinline__ uint4 ld16(const void *p) { return *reinterpret_cast<const uint4 *>(p); }
+__device__ __forceinline__ void st16(void *p, const uint4 &v) { *reinterpret_cast<uint4 *>(p) = v; }
+
+template <typename T> __device__ __forceinline__ void unpack(const uint4 &r, float *f);
+template <> __device__ __forceinline__ void unpack<float>(const uint4 &r, float *f) {
+    f[0] = __uint_as_float(r.x);
+    f[1] = __uint_as_float(r.y);
+    f[2] = __uint_as_float(r.z);
+    f[3] = __uint_as_float(r.w);
+}
+template <> __device__ __forceinline__ void unpack<bf16_t>(const uint4 &r, float *f) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(w[i] << 16);
+        f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+}
+template <> __device__ __forceinline__ void unpack<f16_t>(const uint4 &r, float *f) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = (float)__builtin_bit_cast(f16_t, (uint16_t)(w[i] & 0xffffu));
+        f[2 * i + 1] = (float)__builtin_bit_cast(f16_t, (uint16_t)(w[i] >> 16));
+    }
+}
+
+// Round f to T; `back` receives the float value of what is stored.
+template <typename T> __device__ __forceinline__ uint4 pack(const float *f, float *back);
+template <> __device__ __forceinline__ uint4 pack<float>(const float *f, float *back) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) back[i] = f[i];
+    return make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                      __float_as_uint(f[3]));
+}
+template <> __device__ __forceinline__ uint4 pack<bf16_t>(const float *f, float *back) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = from_f32<bf16_t>(f[2 * i]).x, hi = from_f32<bf16_t>(f[2 * i + 1]).x;
+        back[2 * i] = __uint_as_float(lo << 16);
+        back[2 * i + 1] = __uint_as_float(hi << 16);
+        w[i] = lo | (hi << 16);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+template <> __device__ __forceinline__ uint4 pack<f16_t>(const float *f, float *back) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f16_t a = (f16_t)f[2 * i], b = (f16_t)f[2 * i + 1];
+        back[2 * i] = (float)a;
+        back[2 * i + 1] = (float)b;
+        w[i] = (uint32_t)__builtin_bit_cast(uint16_t, a) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <typename T> __device__ __forceinline__ T cvt_from_f64(double v) {
+    return from_f32<T>((float)v);
+}
+
+// ---------------------------------------------------------------- Philox / Box-Muller
+__device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64_t &c2,
+                                              uint64_t &c3, uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// Z^(0)[i, c] in FP64 (see ifgp_embed in ifgp.h for the rule).
+__device__ __forceinline__ double gaussian_entry(uint64_t seed, int64_t i, int c, int d) {
+    uint64_t c0 = (uint64_t)i + 1, c1 = (uint64_t)c, c2 = 0, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, 0);
+    const double u1 = ((double)(c0 >> 11) + 0.5) * 0x1p-53;
+    const double u2 = ((double)(c1 >> 11) + 0.5) * 0x1p-53;
+    const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    return z / sqrt((double)d);
+}
+
+// ---------------------------------------------------------------- small kernels
+template <typename T>
+__global__ void gaussian_kernel(int64_t N, int d, uint64_t seed, T *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * d) return;
+    const int64_t i = t / d;
+    const int c = (int)(t - i * d);
+    const double z = gaussian_entry(seed, i, c, d);
+    if constexpr (std::is_same<T, double>::value) out[t] = z;
+    else out[t] = cvt_from_f64<T>(z);
+}
+
+// W0[k, c] = s_k Z^(0)[perm[k], c] for c < d, 0 in the padding columns.
+template <typename T, int D>
+__global__ void noise_kernel(int64_t N, int d, uint64_t seed, const int32_t *__restrict__ perm,
+                             const double *__restrict__ s64, T *__restrict__ W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * D) return;
+    const int64_t k = t / D;
+    const int c = (int)(t % D);
+    double v = 0.0;
+    if (c < d) v = s64[k] * gaussian_entry(seed, perm[k], c, d);
+    W[t] = cvt_from_f64<T>(v);
+}
+
+// W0[k, c] = s_k X[perm[k], c] for a caller-supplied X.
+template <typename T, int D>
+__global__ void prep_x_kernel(int64_t N, int d, const float *__restrict__ X,
+                              const int32_t *__restrict__ perm, const double *__restrict__ s64,
+                              T *__restrict__ W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * D) return;
+    const int64_t k = t / D;
+    const int c = (int)(t % D);
+    double v = 0.0;
+    if (c < d) v = s64[k] * (double)X[(int64_t)perm[k] * d + c];
+    W[t] = cvt_from_f64<T>(v);
+}
+
+__global__ void ab_identity_kernel(float *ab, int D) {
+    const int c = threadIdx.x;
+    if (c < D) {
+        ab[c] = 1.0f;
+        ab[D + c] = 0.0f;
+    }
+}
+
+// (D_tau)_ii: Eq. (1) for tau <= 0, literal; deg + tau for tau > 0.
+__device__ __forceinline__ double dtau_of(double deg, double tau, double eps) {
+    if (tau > 0) return deg + tau;
+    const double at = fabs(tau), m = deg - eps;
+    return deg - (at < m ? at : m);
+}
+
+__global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, double tau,
+                              double eps, double *__restrict__ s64) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
+    s64[k] = 1.0 / sqrt(dt);
+}
+
+__global__ void nodeinfo_kernel(int64_t N, const int64_t *__restrict__ irowptr,
+                                const int32_t *__restrict__ icolidx,
+                                const double *__restrict__ s64, double tau, double eps,
+                                float4 *__restrict__ info) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double r = 0.0;
+    for (int64_t e = irowptr[k]; e < irowptr[k + 1]; ++e) r += s64[icolidx[e]];
+    const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
+    info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
+}
+
+__global__ void perm_scales_kernel(int64_t N, const int32_t *__restrict__ perm,
+                                   const double *__restrict__ s64, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) out[perm[k]] = s64[k];
+}
+
+// ---------------------------------------------------------------- the hop
+struct HopArgs {
+    const int64_t *rowptr;   // internal CSR
+    const int32_t *colidx;
+    const void *Win;         // N x D storage, W of the previous hop
+    void *Wout;
+    const float4 *node;      // (s, sqrt(D_tau), r, 0)
+    const float *ab;         // a[D], b[D] of the previous hop's ZNorm
+    double2 *partials;       // [blocks][D] (sum T, sum T^2)
+    int64_t N, n_hub, n_med;
+    int64_t blk_hub_end, blk_med_end, blocks;
+    float alpha, theta;
+};
+
+// Gather-add W rows of neighbours e in [first, end) visited in chunks of U
+// starting every `step`: acc[e] += sum W[j, sl*EPL + e].
+template <typename T, int D>
+__device__ __forceinline__ void gather_add(const int32_t *__restrict__ colidx,
+                                           const char *__restrict__ Win, int64_t first,
+                                           int64_t end, int64_t step, int sl, int lane_base,
+                                           float *acc) {
+    using C = Cfg<T, D>;
+    constexpr int EPL = C::EPL, LPR = C::LPR, QI = C::QI;
+    const int64_t col_off = (int64_t)sl * EPL * (int64_t)sizeof(T);
+    for (int64_t e0 = first; e0 < end; e0 += step) {
+        int32_t idx[QI];
+#pragma unroll
+        for (int q = 0; q < QI; ++q) {
+            const int slot = q * LPR + sl;
+            const int64_t e = e0 + slot;
+            idx[q] = (slot < U && e < end) ? colidx[e] : -1;
+        }
+        uint4 raw[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            int j;
+            if constexpr (LPR == 1) j = idx[k];
+            else j = __shfl(idx[k / LPR], lane_base + (k % LPR), 64);
+            if (j >= 0) raw[k] = ld16(Win + (int64_t)j * (D * (int64_t)sizeof(T)) + col_off);
+            else raw[k] = make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            float f[EPL];
+            unpack<T>(raw[k], f);
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) acc[e] += f[e];
+        }
+    }
+}
+
+// Finish row r from its neighbour sum: tanh, store W = s T, add the stored
+// T to the column statistics.
+template <typename T, int D>
+__device__ __forceinline__ void row_finish(const HopArgs &a, int64_t r, int sl, const float *acc,
+                                           const float *av, const float *bv, double *ssum,
+                                           double *ssq) {
+    using C = Cfg<T, D>;
+    constexpr int EPL = C::EPL;
+    const float4 nd = a.node[r];
+    const int64_t off = (r * D + (int64_t)sl * EPL) * (int64_t)sizeof(T);
+    float xin[EPL];
+    unpack<T>(ld16((const char *)a.Win + off), xin);
+    float wnew[EPL], back[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const float tprev = xin[e] * nd.y;                  // T_i of the previous hop
+        const float zself = fmaf(av[e], tprev, bv[e]);      // Zn_i
+        const float agg = fmaf(av[e], acc[e], bv[e] * nd.z); // sum_j s_j Zn_j
+        const float y = fmaf(a.theta, zself, a.alpha * nd.x * agg);
+        wnew[e] = nd.x * tanhf(y);
+    }
+    st16((char *)a.Wout + off, pack<T>(wnew, back));
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const double t = (double)back[e] * (double)nd.y;  // stored T_i (float product, exact in FP64)
+        ssum[e] += t;
+        ssq[e] += t * t;
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
+    using C = Cfg<T, D>;
+    constexpr int EPL = C::EPL, LPR = C::LPR, RPW = C::RPW;
+    __shared__ float lds_acc[WAVES][D];
+    __shared__ double2 lds_st[WAVES][D];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane / LPR, sl = lane % LPR, lane_base = lane - sl;
+    const char *Win = (const char *)a.Win;
+
+    float av[EPL], bv[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        av[e] = a.ab[sl * EPL + e];
+        bv[e] = a.ab[D + sl * EPL + e];
+    }
+    double ssum[EPL], ssq[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) ssum[e] = ssq[e] = 0.0;
+
+    if (blk < a.blk_hub_end) {
+        // hub: the whole block on one row
+        const int64_t r = blk;
+        float acc[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
+        const int64_t beg = a.rowptr[r], end = a.rowptr[r + 1];
+        gather_add<T, D>(a.colidx, Win, beg + (int64_t)(w * RPW + g) * U, end,
+                         (int64_t)WAVES * RPW * U, sl, lane_base, acc);
+#pragma unroll
+        for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
+        if (g == 0)
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) lds_acc[w][sl * EPL + e] = acc[e];
+        __syncthreads();
+        if (w == 0 && g == 0) {
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int c = sl * EPL + e;
+                acc[e] = ((lds_acc[0][c] + lds_acc[1][c]) + lds_acc[2][c]) + lds_acc[3][c];
+            }
+            row_finish<T, D>(a, r, sl, acc, av, bv, ssum, ssq);
+        }
+    } else if (blk < a.blk_med_end) {
+        // medium: one wave per row
+        const int64_t r = a.n_hub + (blk - a.blk_hub_end) * MED_ROWS_PER_BLOCK + w;
+        if (r < a.n_hub + a.n_med) {
+            float acc[EPL];
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
+            const int64_t beg = a.rowptr[r], end = a.rowptr[r + 1];
+            gather_add<T, D>(a.colidx, Win, beg + (int64_t)g * U, end, (int64_t)RPW * U, sl,
+                             lane_base, acc);
+#pragma unroll
+            for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
+            if (g == 0) row_finish<T, D>(a, r, sl, acc, av, bv, ssum, ssq);
+        }
+    } else {
+        // light: one LPR-lane subgroup per row
+        const int64_t row0 =
+            a.n_hub + a.n_med + (blk - a.blk_med_end) * (int64_t)LIGHT_ROWS_PER_BLOCK;
+        constexpr int PASSES = LIGHT_ROWS_PER_BLOCK / (WAVES * RPW);
+        for (int p = 0; p < PASSES; ++p) {
+            const int64_t r = row0 + (int64_t)p * WAVES * RPW + w * RPW + g;
+            if (r < a.N) {
+                float acc[EPL];
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
+                gather_add<T, D>(a.colidx, Win, a.rowptr[r], a.rowptr[r + 1], (int64_t)U, sl,
+                                 lane_base, acc);
+                row_finish<T, D>(a, r, sl, acc, av, bv, ssum, ssq);
+            }
+        }
+    }
+
+    // block statistics: subgroups (butterfly), then waves in order
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            ssum[e] += __shfl_xor(ssum[e], off, 64);
+            ssq[e] += __shfl_xor(ssq[e], off, 64);
+        }
+    if (g == 0)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) lds_st[w][sl * EPL + e] = make_double2(ssum[e], ssq[e]);
+    __syncthreads();
+    if (tid < D) {
+        double2 t = lds_st[0][tid];
+#pragma unroll
+        for (int ww = 1; ww < WAVES; ++ww) {
+            t.x += lds_st[ww][tid].x;
+            t.y += lds_st[ww][tid].y;
+        }
+        a.partials[blk * D + tid] = t;
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(THREADS) void hop_kernel(const HopArgs a) {
+    hop_block<T, D>(a, blockIdx.x);
+}
+
+// Many graphs in one launch: graph gi owns blocks [blk_start[gi], blk_start[gi+1]).
+template <typename T, int D>
+__global__ __launch_bounds__(THREADS) void hop_batch_kernel(const HopArgs *__restrict__ args,
+                                                            const int64_t *__restrict__ blk_start,
+                                                            int ngraphs) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = ngraphs - 1;
+    while (lo < hi) {  // last gi with blk_start[gi] <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    hop_block<T, D>(args[lo], b - blk_start[lo]);
+}
+
+// mu, sigma per column from the block partials (fixed order), then
+// a = 1/sigma, b = -mu/sigma; a column of zero spread gives a = b = 0.
+struct FinArgs {
+    const double2 *partials;
+    int64_t blocks, N;
+    int D, ddof;
+    float *ab;
+};
+
+__device__ __forceinline__ void finalize_column(const FinArgs &f, int c) {
+    __shared__ double rs[WAVES], rq[WAVES];
+    double s = 0.0, q = 0.0;
+    for (int64_t b = threadIdx.x; b < f.blocks; b += THREADS) {
+        const double2 p = f.partials[b * f.D + c];
+        s += p.x;
+        q += p.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        rs[w] = s;
+        rq[w] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s = ((rs[0] + rs[1]) + rs[2]) + rs[3];
+        q = ((rq[0] + rq[1]) + rq[2]) + rq[3];
+        const double n = (double)f.N;
+        const double mu = s / n;
+        const double den = n - (double)f.ddof;
+        const double var = den > 0 ? (q - s * mu) / den : 0.0;
+        float a = 0.f, b = 0.f;
+        if (var > 0) {
+            const double sd = sqrt(var);
+            a = (float)(1.0 / sd);
+            b = (float)(-mu / sd);
+        }
+        f.ab[c] = a;
+        f.ab[f.D + c] = b;
+    }
+}
+
+__global__ __launch_bounds__(THREADS) void finalize_kernel(const FinArgs f) {
+    finalize_column(f, blockIdx.x);
+}
+
+// grid = (D, graphs)
+__global__ __launch_bounds__(THREADS) void finalize_batch_kernel(const FinArgs *__restrict__ fs) {
+    const FinArgs f = fs[blockIdx.y];
+    if ((int)blockIdx.x < f.D) finalize_column(f, blockIdx.x);
+}
+
+// out[perm[k], c] = sigma(a_c T_k,c + b_c), c < d
+template <typename T, int D>
+__global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
+                                                           const void *__restrict__ Wv,
+                                                           const float4 *__restrict__ node,
+                                                           const float *__restrict__ ab,
+                                                           const int32_t *__restrict__ perm,
+                                                           float *__restrict__ out) {
+    using C = Cfg<T, D>;
+    constexpr int EPL = C::EPL, LPR = C::LPR;
+    const int64_t gl = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    const int64_t k = gl / LPR;
+    const int sl = (int)(gl % LPR);
+    if (k >= N) return;
+    float t[EPL];
+    unpack<T>(ld16((const char *)Wv + (k * D + (int64_t)sl * EPL) * (int64_t)sizeof(T)), t);
+    const float sq = node[k].y;
+    float *o = out + (int64_t)perm[k] * d;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const int c = sl * EPL + e;
+        if (c < d) {
+            const float z = fmaf(ab[c], t[e] * sq, ab[D + c]);
+            o[c] = 1.0f / (1.0f + expf(-z));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+template <typename T, int D> int64_t blocks_for(const GraphData &g) {
+    const int64_t n_light = g.N - g.n_hub - g.n_med;
+    return g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK) +
+           ceil_div(n_light, LIGHT_ROWS_PER_BLOCK);
+}
+
+#define IFGP_WIDTHS(T, Dp, CALL)                                  \
+    switch (Dp) {                                                 \
+    case 8: return CALL(T, 8);                                    \
+    case 16: return CALL(T, 16);                                  \
+    case 32: return CALL(T, 32);                                  \
+    case 64: return CALL(T, 64);                                  \
+    case 128: return CALL(T, 128);                                \
+    case 256: return CALL(T, 256);                                \
+    default: break;                                               \
+    }
+
+#define IFGP_DISPATCH(storage, Dp, CALL)                          \
+    do {                                                          \
+        switch (storage) {                                        \
+        case IFGP_F32: IFGP_WIDTHS(float, Dp, CALL) break;        \
+        case IFGP_BF16: IFGP_WIDTHS(bf16_t, Dp, CALL) break;      \
+        case IFGP_F16: IFGP_WIDTHS(f16_t, Dp, CALL) break;        \
+        default: break;                                           \
+        }                                                         \
+    } while (0)
+
+HopArgs make_hop_args(ifgp_graph_s *h) {
+    const GraphData &g = h->g;
+    const Job &j = h->job;
+    HopArgs a{};
+    a.rowptr = g.irowptr.as<int64_t>();
+    a.colidx = g.icolidx.as<int32_t>();
+    a.Win = h->ws.feat[j.cur].p;
+    a.Wout = h->ws.feat[1 - j.cur].p;
+    a.node = h->sc.nodeinfo.as<float4>();
+    a.ab = h->ws.ab.as<float>();
+    a.partials = h->ws.partials.as<double2>();
+    a.N = g.N;
+    a.n_hub = g.n_hub;
+    a.n_med = g.n_med;
+    a.blk_hub_end = g.n_hub;
+    a.blk_med_end = g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK);
+    a.blocks = hop_blocks(g, j.Dp, j.storage);
+    a.alpha = (float)j.alpha;
+    a.theta = (float)j.theta;
+    return a;
+}
+
+FinArgs make_fin_args(ifgp_graph_s *h) {
+    FinArgs f{};
+    f.partials = h->ws.partials.as<double2>();
+    f.blocks = hop_blocks(h->g, h->job.Dp, h->job.storage);
+    f.N = h->g.N;
+    f.D = h->job.Dp;
+    f.ddof = h->job.ddof;
+    f.ab = h->ws.ab.as<float>();
+    return f;
+}
+
+ifgp_status launch_hop(const HopArgs &a, int storage, int Dp, hipStream_t s) {
+#define HOP_CALL(T, D) (hop_kernel<T, D><<<(unsigned)a.blocks, THREADS, 0, s>>>(a), IFGP_OK)
+    IFGP_DISPATCH(storage, Dp, HOP_CALL);
+#undef HOP_CALL
+    set_error("unsupported storage/width");
+    return IFGP_E_INVALID;
+}
+
+ifgp_status launch_hop_batch(const HopArgs *args_dev, const int64_t *blk_start_dev, int n,
+                             int64_t total_blocks, int storage, int Dp, hipStream_t s) {
+#define HOPB_CALL(T, D)                                                                         \
+    (hop_batch_kernel<T, D><<<(unsigned)total_blocks, THREADS, 0, s>>>(args_dev, blk_start_dev, \
+                                                                       n),                      \
+     IFGP_OK)
+    IFGP_DISPATCH(storage, Dp, HOPB_CALL);
+#undef HOPB_CALL
+    set_error("unsupported storage/width");
+    return IFGP_E_INVALID;
+}
+
+ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStream_t s) {
+    const Job &j = h->job;
+    const int64_t n = h->g.N * j.Dp;
+    const unsigned grid = (unsigned)ceil_div(n, THREADS);
+    void *W = h->ws.feat[0].p;
+    const int32_t *perm = h->g.perm.as<int32_t>();
+    const double *s64 = h->sc.s64.as<double>();
+    const int64_t N = h->g.N;
+    const int d = j.d;
+#define NOISE_CALL(T, D)                                                                        \
+    (X ? (prep_x_kernel<T, D><<<grid, THREADS, 0, s>>>(N, d, X, perm, s64, (T *)W), IFGP_OK)    \
+       : (noise_kernel<T, D><<<grid, THREADS, 0, s>>>(N, d, seed, perm, s64, (T *)W), IFGP_OK))
+    IFGP_DISPATCH(j.storage, j.Dp, NOISE_CALL);
+#undef NOISE_CALL
+    set_error("unsupported storage/width");
+    return IFGP_E_INVALID;
+}
+
+ifgp_status launch_epilogue(ifgp_graph_s *h, hipStream_t s) {
+    const Job &j = h->job;
+    const int64_t N = h->g.N;
+    const void *W = h->ws.feat[j.cur].p;
+    const float4 *node = h->sc.nodeinfo.as<float4>();
+    const float *ab = h->ws.ab.as<float>();
+    const int32_t *perm = h->g.perm.as<int32_t>();
+    float *out = j.out;
+    const int d = j.d;
+#define EPI_CALL(T, D)                                                                          \
+    (epilogue_kernel<T, D><<<(unsigned)ceil_div(N * Cfg<T, D>::LPR, THREADS), THREADS, 0, s>>>( \
+         N, d, W, node, ab, perm, out),                                                         \
+     IFGP_OK)
+    IFGP_DISPATCH(j.storage, j.Dp, EPI_CALL);
+#undef EPI_CALL
+    set_error("unsupported storage/width");
+    return IFGP_E_INVALID;
+}
+
+ifgp_status validate_params(const ifgp_params &p) {
+    if (!std::isfinite(p.alpha) || !std::isfinite(p.theta) || !(p.eps > 0) ||
+        !std::isfinite(p.eps)) {
+        set_error("alpha and theta must be finite and eps > 0");
+        return IFGP_E_INVALID;
+    }
+    if (p.znorm_ddof != 0 && p.znorm_ddof != 1) {
+        set_error("znorm_ddof must be 0 or 1");
+        return IFGP_E_INVALID;
+    }
+    if (p.storage != IFGP_F32 && p.storage != IFGP_BF16 && p.storage != IFGP_F16) {
+        set_error("storage must be IFGP_F32, IFGP_BF16 or IFGP_F16");
+        return IFGP_E_INVALID;
+    }
+    return IFGP_OK;
+}
+
+ifgp_status record_event(ifgp_graph_s *h, hipStream_t s, bool start) {
+    if (!h->timing) return IFGP_OK;
+    hipEvent_t ev;
+    IFGP_HIP(hipEventCreate(&ev));
+    IFGP_HIP(hipEventRecord(ev, s));
+    if (start) h->events.push_back({ev, nullptr});
+    else h->events.back().second = ev;
+    return IFGP_OK;
+}
+
+}  // namespace
+
+int64_t hop_blocks(const GraphData &g, int Dp, int storage) {
+    (void)Dp;
+    (void)storage;
+    // block count does not depend on the width: every class has a fixed
+    // number of rows per block
+    return blocks_for<float, 64>(g);
+}
+
+ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
+                                  hipStream_t s) {
+    const int64_t n = N * d;
+    if (n == 0) return IFGP_OK;
+    const unsigned grid = (unsigned)ceil_div(n, THREADS);
+    switch (dtype) {
+    case IFGP_F64: gaussian_kernel<double><<<grid, THREADS, 0, s>>>(N, d, seed, (double *)out); break;
+    case IFGP_F32: gaussian_kernel<float><<<grid, THREADS, 0, s>>>(N, d, seed, (float *)out); break;
+    case IFGP_BF16: gaussian_kernel<bf16_t><<<grid, THREADS, 0, s>>>(N, d, seed, (bf16_t *)out); break;
+    case IFGP_F16: gaussian_kernel<f16_t><<<grid, THREADS, 0, s>>>(N, d, seed, (f16_t *)out); break;
+    default: set_error("unsupported dtype"); return IFGP_E_INVALID;
+    }
+    IFGP_LAUNCHED();
+    return IFGP_OK;
+}
+
+ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
+    Scales &sc = h->sc;
+    if (sc.valid && sc.tau == tau && sc.eps == eps) return IFGP_OK;
+    sc.valid = false;
+    const GraphData &g = h->g;
+    IFGP_TRY(ensure(sc.s64, sizeof(double) * g.N, s));
+    IFGP_TRY(ensure(sc.nodeinfo, sizeof(float4) * g.N, s));
+    const unsigned grid = (unsigned)ceil_div(g.N, THREADS);
+    scales_kernel<<<grid, THREADS, 0, s>>>(g.N, g.irowptr.as<int64_t>(), tau, eps,
+                                           sc.s64.as<double>());
+    IFGP_LAUNCHED();
+    nodeinfo_kernel<<<grid, THREADS, 0, s>>>(g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
+                                             sc.s64.as<double>(), tau, eps,
+                                             sc.nodeinfo.as<float4>());
+    IFGP_LAUNCHED();
+    sc.tau = tau;
+    sc.eps = eps;
+    sc.valid = true;
+    return IFGP_OK;
+}
+
+ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s) {
+    const int64_t N = h->g.N;
+    Buf tmp;
+    IFGP_TRY(alloc(tmp, sizeof(double) * N, s));
+    perm_scales_kernel<<<(unsigned)ceil_div(N, THREADS), THREADS, 0, s>>>(
+        N, h->g.perm.as<int32_t>(), h->sc.s64.as<double>(), tmp.as<double>());
+    IFGP_LAUNCHED();
+    IFGP_HIP(hipMemcpyAsync(s_host, tmp.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    IFGP_HIP(hipStreamSynchronize(s));
+    return IFGP_OK;
+}
+
+ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
+                      const float *X, const ifgp_params &p, float *out, hipStream_t s) {
+    IFGP_TRY(validate_params(p));
+    if (!std::isfinite(tau)) {
+        set_error("tau must be finite");
+        return IFGP_E_INVALID;
+    }
+    if (K < 0 || d < 1 || d > 256 || !out) {
+        set_error("need K >= 0, 1 <= d <= 256 and an output buffer");
+        return IFGP_E_INVALID;
+    }
+    const int Dp = padded_width(d);
+    h->job = Job{};
+    IFGP_TRY(ensure_scales(h, tau, p.eps, s));
+    const GraphData &g = h->g;
+    const size_t fb = (size_t)g.N * Dp * dtype_bytes(p.storage);
+    IFGP_TRY(ensure(h->ws.feat[0], fb, s));
+    IFGP_TRY(ensure(h->ws.feat[1], fb, s));
+    IFGP_TRY(ensure(h->ws.partials, sizeof(double2) * Dp * hop_blocks(g, Dp, p.storage), s));
+    IFGP_TRY(ensure(h->ws.ab, sizeof(float) * 2 * Dp, s));
+    Job &j = h->job;
+    j.K = K;
+    j.d = d;
+    j.Dp = Dp;
+    j.hop = 0;
+    j.storage = p.storage;
+    j.alpha = p.alpha;
+    j.theta = p.theta;
+    j.ddof = p.znorm_ddof;
+    j.cur = 0;
+    j.out = out;
+    IFGP_TRY(launch_noise(h, seed, X, s));
+    IFGP_LAUNCHED();
+    ab_identity_kernel<<<1, THREADS, 0, s>>>(h->ws.ab.as<float>(), Dp);
+    IFGP_LAUNCHED();
+    j.active = true;
+    if (K == 0) {
+        IFGP_TRY(launch_epilogue(h, s));
+        IFGP_LAUNCHED();
+        j.done = true;
+    }
+    return IFGP_OK;
+}
+
+ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
+    // Group unfinished jobs by (storage, width); one hop launch and one
+    // finalize launch per group.
+    struct Group {
+        int storage, Dp;
+        std::vector<ifgp_graph_s *> members;
+    };
+    std::vector<Group> groups;
+    for (int i = 0; i < n; ++i) {
+        ifgp_graph_s *h = hs[i];
+        if (!h->job.active || h->job.done) continue;
+        Group *gp = nullptr;
+        for (auto &G : groups)
+            if (G.storage == h->job.storage && G.Dp == h->job.Dp) gp = &G;
+        if (!gp) {
+            groups.push_back({h->job.storage, h->job.Dp, {}});
+            gp = &groups.back();
+        }
+        gp->members.push_back(h);
+    }
+    for (auto &G : groups) {
+        if (G.members.size() == 1) {
+            ifgp_graph_s *h = G.members[0];
+            const HopArgs a = make_hop_args(h);
+            IFGP_TRY(record_event(h, s, true));
+            IFGP_TRY(launch_hop(a, G.storage, G.Dp, s));
+            IFGP_LAUNCHED();
+            IFGP_TRY(record_event(h, s, false));
+            const FinArgs f = make_fin_args(h);
+            finalize_kernel<<<(unsigned)G.Dp, THREADS, 0, s>>>(f);
+            IFGP_LAUNCHED();
+        } else {
+            const int m = (int)G.members.size();
+            std::vector<HopArgs> ha(m);
+            std::vector<FinArgs> fa(m);
+            std::vector<int64_t> start(m + 1, 0);
+            for (int i = 0; i < m; ++i) {
+                ha[i] = make_hop_args(G.members[i]);
+                fa[i] = make_fin_args(G.members[i]);
+                start[i + 1] = start[i] + ha[i].blocks;
+            }
+            // argument tables: staged through the first member's stream-ordered scratch
+            Buf tab;
+            const size_t bytes = sizeof(HopArgs) * m + sizeof(FinArgs) * m + sizeof(int64_t) * (m + 1);
+            IFGP_TRY(alloc(tab, bytes, s));
+            std::vector<char> host(bytes);
+            std::memcpy(host.data(), ha.data(), sizeof(HopArgs) * m);
+            std::memcpy(host.data() + sizeof(HopArgs) * m, fa.data(), sizeof(FinArgs) * m);
+            std::memcpy(host.data() + (sizeof(HopArgs) + sizeof(FinArgs)) * m, start.data(),
+                   sizeof(int64_t) * (m + 1));
+            IFGP_HIP(hipMemcpyAsync(tab.p, host.data(), bytes, hipMemcpyHostToDevice, s));
+            const HopArgs *ha_d = tab.as<HopArgs>();
+            const FinArgs *fa_d = (const FinArgs *)((char *)tab.p + sizeof(HopArgs) * m);
+            const int64_t *st_d =
+                (const int64_t *)((char *)tab.p + (sizeof(HopArgs) + sizeof(FinArgs)) * m);
+            for (auto *h : G.members) IFGP_TRY(record_event(h, s, true));
+            IFGP_TRY(launch_hop_batch(ha_d, st_d, m, start[m], G.storage, G.Dp, s));
+            IFGP_LAUNCHED();
+            for (auto *h : G.members) IFGP_TRY(record_event(h, s, false));
+            finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)m), THREADS, 0, s>>>(fa_d);
+            IFGP_LAUNCHED();
+            // the pageable copy above completed before returning; `tab` is
+            // released stream-ordered by the allocator hook
+            IFGP_HIP(hipStreamSynchronize(s));
+        }
+        for (auto *h : G.members) {
+            Job &j = h->job;
+            j.cur = 1 - j.cur;
+            j.hop += 1;
+            if (j.hop >= j.K) {
+                IFGP_TRY(launch_epilogue(h, s));
+                IFGP_LAUNCHED();
+                j.done = true;
+            }
+        }
+    }
+    return IFGP_OK;
+}
+
+}  // namespace ifgp

@@ -1,0 +1,102 @@
+// Declarations shared between the libifgp translation units.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace ifgp {
+
+// ---- primitives.hip
+template <typename In>
+ifgp_status exclusive_scan(const In *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
+ifgp_status fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+// Sorts n keys whose set bits lie below `bits`; a and b are both n long; on
+// return *sorted is whichever of them holds the ascending result.
+ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int bits, hipStream_t s,
+                           uint64_t **sorted);
+
+// Row classes of the hop kernel, by degree.  Rows are kept in descending-
+// degree order, so each class is a contiguous range of internal rows.
+constexpr int64_t HUB_DEGREE = 4096;  // >= : one 256-thread block per row
+constexpr int64_t MED_DEGREE = 256;   // >= : one wave per row
+constexpr int MED_ROWS_PER_BLOCK = 4;
+constexpr int LIGHT_ROWS_PER_BLOCK = 256;
+
+// Canonical graph plus the execution plan of the hop kernel.
+struct GraphData {
+    int64_t N = 0, nnz = 0;
+    int64_t self_loops = 0, dups = 0;   // totals over every edge ever added
+    int32_t max_deg = 0;
+    // canonical CSR over original ids, columns ascending
+    Buf rowptr;   // int64 N+1
+    Buf colidx;   // int32 nnz
+    Buf deg;      // int32 N
+    // plan: internal row k holds node perm[k]; rows sorted by degree, descending
+    Buf perm;     // int32 N
+    Buf iperm;    // int32 N (node -> internal row)
+    Buf irowptr;  // int64 N+1
+    Buf icolidx;  // int32 nnz, internal ids
+    int64_t n_hub = 0, n_med = 0;
+};
+
+// Per-(tau, eps) node quantities in internal order.
+struct Scales {
+    bool valid = false;
+    double tau = 0, eps = 0;
+    Buf s64;       // double N: (D_tau)^{-1/2}
+    Buf nodeinfo;  // float4 N: (s, sqrt(D_tau), sum_{j in N(i)} s_j, 0)
+};
+
+struct Workspace {
+    Buf feat[2];    // N x Dp storage elements each
+    Buf partials;   // double2 [hop blocks][Dp]
+    Buf ab;         // float [2][Dp]: per-column scale a = 1/sigma and shift b = -mu/sigma
+};
+
+struct Job {
+    bool active = false;
+    int32_t K = 0, d = 0, Dp = 0, hop = 0;
+    int32_t storage = IFGP_F32;
+    double alpha = 1, theta = 0.1;
+    int32_t ddof = 0;
+    int cur = 0;      // which feat buffer holds the current hop's input
+    float *out = nullptr;
+    bool done = false;
+};
+
+}  // namespace ifgp
+
+struct ifgp_graph_s {
+    int device = 0;
+    hipStream_t stream = nullptr;   // stream of the most recent call
+    ifgp::GraphData g;
+    ifgp::Scales sc;
+    ifgp::Workspace ws;
+    ifgp::Job job;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+namespace ifgp {
+
+// ---- graph.hip
+// Build the canonical CSR and plan from edges already in device memory.
+ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
+                               hipStream_t s, GraphData &out);
+// Merge device edges into `in`, producing `out` (in is left unchanged).
+ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const int64_t *dst,
+                               int64_t E, int64_t new_N, hipStream_t s, GraphData &out);
+
+// ---- ffp.hip
+ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s);
+ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
+                      const float *X, const ifgp_params &p, float *out, hipStream_t s);
+// Advance every listed job by one hop (one launch per storage/width class).
+ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s);
+int64_t hop_blocks(const GraphData &g, int Dp, int storage);
+ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
+                                  hipStream_t s);
+ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s);
+
+}  // namespace ifgp

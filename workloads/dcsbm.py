@@ -118,8 +118,21 @@ def dcsbm(N: int, B: int, mean_deg: float = 20.0, ratio: float = 2.5,
     pb /= pb.sum()
     total = cum[-1]
 
+    # Inverse-CDF lookup through a guide table (Chen & Asau 1974): bucket b of
+    # width h starts the search at the first slot whose cumulative propensity
+    # exceeds b*h; a few vectorised forward steps finish it.  Same result as
+    # searchsorted(cum, vals, side="right").
+    h = total / N
+    guide = np.searchsorted(cum, np.arange(N) * h, side="right")
+
     def pick(vals):
-        idx = np.searchsorted(cum, vals, side="right")
+        b = np.clip((vals / h).astype(np.int64) - 1, 0, N - 1)
+        idx = guide[b]
+        while True:
+            m = np.flatnonzero((idx < N - 1) & (cum[np.minimum(idx, N - 1)] <= vals))
+            if m.size == 0:
+                break
+            idx[m] += 1
         return node_of_slot[np.minimum(idx, N - 1)]
 
     def draw_within(n):
