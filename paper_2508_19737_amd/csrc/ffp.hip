@@ -458,7 +458,14 @@ __device__ __forceinline__ void finalize_column(const FinArgs &f, int c) {
         const double n = (double)f.N;
         const double mu = s / n;
         const double den = n - (double)f.ddof;
-        const double var = den > 0 ? (q - s * mu) / den : 0.0;
+        // s*mu rounded on its own (no fused multiply-add), so that one row, or
+        // identical rows summed exactly, give a variance of exactly zero
+        double var = 0.0;
+        if (den > 0) {
+#pragma clang fp contract(off)
+            const double smu = s * mu;
+            var = (q - smu) / den;
+        }
         float a = 0.f, b = 0.f;
         if (var > 0) {
             const double sd = sqrt(var);
