@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--tau", type=float, default=-1.0)
     ap.add_argument("--cpu-cols", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB copy kernel (reads 1 GiB, writes 1 GiB) so "
+                         "that profiler byte counters can be scaled against known traffic")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -103,6 +106,13 @@ def main():
 
     torch.cuda.set_device(0)
     ifgp.use_torch_allocator()
+    if a.calibrate:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
     say(f"generating DC-SBM N={a.N} B={a.blocks}")
     g = dcsbm(a.N, a.blocks, mean_deg=20.0, ratio=2.5, seed=0)
     src = torch.as_tensor(g.src, device="cuda")

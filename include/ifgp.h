@@ -116,10 +116,13 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
  *   tau     degree correction; tau <= 0 uses Eq. (1), tau > 0 uses D + tau I
  *   K       number of hops, K >= 0 (K = 0 returns sigma(Z^(0)))
  *   d       embedding dimension, 1 <= d <= 256
- *   seed    Z^(0)[i, c] is a pure function of (seed, i, c): Philox4x64-10
- *           (Salmon et al., SC'11) with key (seed, 0) and counter
- *           (i + 1, c, 0, 0), Box-Muller on output words 0 and 1 mapped to
- *           ((w >> 11) + 0.5) 2^-53, scaled by d^{-1/2}
+ *   seed    Z^(0)[i, c] is a pure function of (seed, i, c): with q = c / 4,
+ *           the Philox4x64-10 block (Salmon et al., SC'11) with key (seed, 0)
+ *           and counter (i + 1, q, 0, 0) gives words w0..w3, each mapped to
+ *           u = ((w >> 11) + 0.5) 2^-53; Box-Muller (Box & Muller 1958) on
+ *           (u0, u1) gives columns 4q, 4q+1 as r cos(phi), r sin(phi) with
+ *           r = sqrt(-2 ln u0), phi = 2 pi u1, and on (u2, u3) columns 4q+2,
+ *           4q+3; every value is divided by sqrt(d)
  *   p       parameters, NULL = ifgp_default_params
  *   out     device, N x d FP32, row-major, caller-owned; row i is node i
  * Errors: IFGP_E_INVALID (d, K, tau not finite, params), IFGP_E_OOM,

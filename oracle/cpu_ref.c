@@ -10,7 +10,8 @@
  *   D_tau     Eq. (1) for tau <= 0 (literal form), D + tau I for tau > 0
  *   s_i       (D_tau)_ii^{-1/2}
  *   Z^(0)     N(0, 1/d): Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
- *             counter (i+1, c, 0, 0), Box-Muller on words 0 and 1
+ *             counter (i+1, c/4, 0, 0); Box-Muller on words (0, 1) gives
+ *             columns 4q, 4q+1 (cos, sin), on words (2, 3) columns 4q+2, 4q+3
  *   hop       Y = theta Z + alpha S A S Z        (Eq. (3))
  *   layer     Z = ZNorm(tanh(Y)), column z-score with divisor N - ddof (Eq. (4))
  *   output    sigma(Z^(K))                       (Eq. (4))
@@ -51,9 +52,13 @@ void oracle_gaussian_input(int64_t N, int32_t d, uint64_t seed, double *X)
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         for (int32_t c = 0; c < d; ++c) {
-            uint64_t ctr[4] = {(uint64_t)i + 1, (uint64_t)c, 0, 0}, o[4];
+            uint64_t ctr[4] = {(uint64_t)i + 1, (uint64_t)(c / 4), 0, 0}, o[4];
             oracle_philox4x64_10(ctr, seed, 0, o);
-            double z = sqrt(-2.0 * log(u53(o[0]))) * cos(2.0 * M_PI * u53(o[1]));
+            const int j = c % 4;
+            const double ua = u53(j < 2 ? o[0] : o[2]);
+            const double ub = u53(j < 2 ? o[1] : o[3]);
+            const double r = sqrt(-2.0 * log(ua)), phi = 2.0 * M_PI * ub;
+            const double z = (j % 2 == 0) ? r * cos(phi) : r * sin(phi);
             X[i * d + c] = z / sqrt((double)d);
         }
     }

@@ -143,22 +143,30 @@ def uniform53(o):
 def gaussian_input(N, d, seed, rows=None, cols=None):
     """Z^(0)[i, c] ~ N(0, 1/d), variance 1/d (standard deviation d^{-1/2}).
 
-    Entry (i, c) is a pure function of (seed, i, c): the Philox4x64-10 block
-    with key (seed, 0) and counter (i + 1, c, 0, 0) gives words o0, o1;
-    u1 = uniform53(o0), u2 = uniform53(o1); the Box-Muller transform
-    (Box & Muller 1958) gives sqrt(-2 ln u1) cos(2 pi u2), scaled by d^{-1/2}.
-    `rows`/`cols` select a sub-block (default all).  Parity with the paper's
-    own random draw is unpinned: the paper does not name its generator.
+    Entry (i, c) is a pure function of (seed, i, c).  With q = c // 4, the
+    Philox4x64-10 block with key (seed, 0) and counter (i + 1, q, 0, 0) gives
+    words o0..o3 and uniforms u_k = uniform53(o_k).  The Box-Muller transform
+    (Box & Muller 1958) of the pair (u0, u1), r = sqrt(-2 ln u0),
+    phi = 2 pi u1, gives columns 4q (r cos phi) and 4q+1 (r sin phi); the pair
+    (u2, u3) gives columns 4q+2 and 4q+3 the same way.  Each value is scaled
+    by d^{-1/2}.  `rows`/`cols` select a sub-block (default all).  Parity with
+    the paper's own random draw is unpinned: the paper does not name its
+    generator.
     """
     rows = np.arange(N, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
     cols = np.arange(d, dtype=np.uint64) if cols is None else np.asarray(cols, dtype=np.uint64)
     ii, cc = np.meshgrid(rows, cols, indexing="ij")
+    q = cc // np.uint64(4)
+    j = (cc % np.uint64(4)).astype(np.int64)
     with np.errstate(over="ignore"):
-        o0, o1, _, _ = philox4x64_10(ii + np.uint64(1), cc, np.zeros_like(ii), np.zeros_like(ii),
-                                     np.uint64(seed), 0)
-    u1 = uniform53(o0)
-    u2 = uniform53(o1)
-    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+        o0, o1, o2, o3 = philox4x64_10(ii + np.uint64(1), q, np.zeros_like(ii), np.zeros_like(ii),
+                                       np.uint64(seed), 0)
+    first = j < 2
+    ua = uniform53(np.where(first, o0, o2))
+    ub = uniform53(np.where(first, o1, o3))
+    r = np.sqrt(-2.0 * np.log(ua))
+    phi = 2.0 * np.pi * ub
+    z = np.where(j % 2 == 0, r * np.cos(phi), r * np.sin(phi))
     return z / np.sqrt(float(d))
 
 

@@ -131,39 +131,61 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64
     }
 }
 
-// Z^(0)[i, c] in FP64 (see ifgp_embed in ifgp.h for the rule).
-__device__ __forceinline__ double gaussian_entry(uint64_t seed, int64_t i, int c, int d) {
-    uint64_t c0 = (uint64_t)i + 1, c1 = (uint64_t)c, c2 = 0, c3 = 0;
+// Z^(0)[i, 4q .. 4q+3] in FP64 (see ifgp_embed in ifgp.h for the rule): one
+// Philox4x64-10 block, two Box-Muller pairs (cos and sin of each).
+__device__ __forceinline__ void gaussian4(uint64_t seed, int64_t i, int64_t q, int d, double *z) {
+    uint64_t c0 = (uint64_t)i + 1, c1 = (uint64_t)q, c2 = 0, c3 = 0;
     philox4x64_10(c0, c1, c2, c3, seed, 0);
-    const double u1 = ((double)(c0 >> 11) + 0.5) * 0x1p-53;
-    const double u2 = ((double)(c1 >> 11) + 0.5) * 0x1p-53;
-    const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-    return z / sqrt((double)d);
+    const uint64_t w[4] = {c0, c1, c2, c3};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double ua = ((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53;
+        const double ub = ((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53;
+        const double r = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincos(2.0 * M_PI * ub, &sn, &cs);
+        z[2 * p] = (r * cs) / sqrt((double)d);
+        z[2 * p + 1] = (r * sn) / sqrt((double)d);
+    }
 }
 
 // ---------------------------------------------------------------- small kernels
 template <typename T>
 __global__ void gaussian_kernel(int64_t N, int d, uint64_t seed, T *out) {
+    const int64_t nq = (d + 3) / 4;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * d) return;
-    const int64_t i = t / d;
-    const int c = (int)(t - i * d);
-    const double z = gaussian_entry(seed, i, c, d);
-    if constexpr (std::is_same<T, double>::value) out[t] = z;
-    else out[t] = cvt_from_f64<T>(z);
+    if (t >= N * nq) return;
+    const int64_t i = t / nq, q = t - i * nq;
+    double z[4];
+    gaussian4(seed, i, q, d, z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t c = 4 * q + j;
+        if (c < d) {
+            if constexpr (std::is_same<T, double>::value) out[i * d + c] = z[j];
+            else out[i * d + c] = cvt_from_f64<T>(z[j]);
+        }
+    }
 }
 
-// W0[k, c] = s_k Z^(0)[perm[k], c] for c < d, 0 in the padding columns.
+// W0[k, c] = s_k Z^(0)[perm[k], c] for c < d, 0 in the padding columns; one
+// thread per group of four columns.
 template <typename T, int D>
 __global__ void noise_kernel(int64_t N, int d, uint64_t seed, const int32_t *__restrict__ perm,
                              const double *__restrict__ s64, T *__restrict__ W) {
+    constexpr int NQ = D / 4;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * D) return;
-    const int64_t k = t / D;
-    const int c = (int)(t % D);
-    double v = 0.0;
-    if (c < d) v = s64[k] * gaussian_entry(seed, perm[k], c, d);
-    W[t] = cvt_from_f64<T>(v);
+    if (t >= N * NQ) return;
+    const int64_t k = t / NQ;
+    const int q = (int)(t % NQ);
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (4 * q < d) gaussian4(seed, perm[k], q, d, z);
+    const double sk = s64[k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = 4 * q + j;
+        W[k * D + c] = cvt_from_f64<T>(c < d ? sk * z[j] : 0.0);
+    }
 }
 
 // W0[k, c] = s_k X[perm[k], c] for a caller-supplied X.
@@ -203,16 +225,31 @@ __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, do
     s64[k] = 1.0 / sqrt(dt);
 }
 
-__global__ void nodeinfo_kernel(int64_t N, const int64_t *__restrict__ irowptr,
-                                const int32_t *__restrict__ icolidx,
-                                const double *__restrict__ s64, double tau, double eps,
-                                float4 *__restrict__ info) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+// 16 lanes per row: r_k = sum of s over the row's neighbours, lanes take
+// strided entries and combine by a fixed butterfly (deterministic order).
+constexpr int NI_LANES = 16;
+__global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N,
+                                                           const int64_t *__restrict__ irowptr,
+                                                           const int32_t *__restrict__ icolidx,
+                                                           const double *__restrict__ s64,
+                                                           double tau, double eps,
+                                                           float4 *__restrict__ info) {
+    const int64_t k = (int64_t)blockIdx.x * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
+    const int l = threadIdx.x % NI_LANES;
+    const bool live = k < N;
     double r = 0.0;
-    for (int64_t e = irowptr[k]; e < irowptr[k + 1]; ++e) r += s64[icolidx[e]];
-    const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
-    info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
+    int64_t beg = 0, end = 0;
+    if (live) {
+        beg = irowptr[k];
+        end = irowptr[k + 1];
+        for (int64_t e = beg + l; e < end; e += NI_LANES) r += s64[icolidx[e]];
+    }
+#pragma unroll
+    for (int off = NI_LANES / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, NI_LANES);
+    if (live && l == 0) {
+        const double dt = dtau_of((double)(end - beg), tau, eps);
+        info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
+    }
 }
 
 __global__ void perm_scales_kernel(int64_t N, const int32_t *__restrict__ perm,
@@ -487,7 +524,31 @@ __global__ __launch_bounds__(THREADS) void finalize_batch_kernel(const FinArgs *
     if ((int)blockIdx.x < f.D) finalize_column(f, blockIdx.x);
 }
 
-// out[perm[k], c] = sigma(a_c T_k,c + b_c), c < d
+// Four consecutive storage elements as floats (8- or 16-byte load).
+template <typename T> __device__ __forceinline__ void load4(const T *p, float *f);
+template <> __device__ __forceinline__ void load4<float>(const float *p, float *f) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    f[0] = v.x;
+    f[1] = v.y;
+    f[2] = v.z;
+    f[3] = v.w;
+}
+template <> __device__ __forceinline__ void load4<bf16_t>(const bf16_t *p, float *f) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    f[0] = __uint_as_float(v.x << 16);
+    f[1] = __uint_as_float(v.x & 0xffff0000u);
+    f[2] = __uint_as_float(v.y << 16);
+    f[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+template <> __device__ __forceinline__ void load4<f16_t>(const f16_t *p, float *f) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    f[0] = (float)__builtin_bit_cast(f16_t, (uint16_t)(v.x & 0xffffu));
+    f[1] = (float)__builtin_bit_cast(f16_t, (uint16_t)(v.x >> 16));
+    f[2] = (float)__builtin_bit_cast(f16_t, (uint16_t)(v.y & 0xffffu));
+    f[3] = (float)__builtin_bit_cast(f16_t, (uint16_t)(v.y >> 16));
+}
+
+// out[perm[k], c] = sigma(a_c T_k,c + b_c), c < d; one thread per four columns.
 template <typename T, int D>
 __global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
                                                            const void *__restrict__ Wv,
@@ -495,23 +556,27 @@ __global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
                                                            const float *__restrict__ ab,
                                                            const int32_t *__restrict__ perm,
                                                            float *__restrict__ out) {
-    using C = Cfg<T, D>;
-    constexpr int EPL = C::EPL, LPR = C::LPR;
+    constexpr int NQ = D / 4;
     const int64_t gl = (int64_t)blockIdx.x * THREADS + threadIdx.x;
-    const int64_t k = gl / LPR;
-    const int sl = (int)(gl % LPR);
-    if (k >= N) return;
-    float t[EPL];
-    unpack<T>(ld16((const char *)Wv + (k * D + (int64_t)sl * EPL) * (int64_t)sizeof(T)), t);
+    const int64_t k = gl / NQ;
+    const int c0 = (int)(gl % NQ) * 4;
+    if (k >= N || c0 >= d) return;
+    float t[4];
+    load4<T>((const T *)Wv + k * D + c0, t);
     const float sq = node[k].y;
-    float *o = out + (int64_t)perm[k] * d;
+    float z[4];
 #pragma unroll
-    for (int e = 0; e < EPL; ++e) {
-        const int c = sl * EPL + e;
-        if (c < d) {
-            const float z = fmaf(ab[c], t[e] * sq, ab[D + c]);
-            o[c] = 1.0f / (1.0f + expf(-z));
-        }
+    for (int e = 0; e < 4; ++e) {
+        const float x = fmaf(ab[c0 + e], t[e] * sq, ab[D + c0 + e]);
+        z[e] = 1.0f / (1.0f + expf(-x));
+    }
+    float *o = out + (int64_t)perm[k] * d + c0;
+    if ((d & 3) == 0) {
+        *reinterpret_cast<float4 *>(o) = make_float4(z[0], z[1], z[2], z[3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (c0 + e < d) o[e] = z[e];
     }
 }
 
@@ -600,6 +665,7 @@ ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStre
     const Job &j = h->job;
     const int64_t n = h->g.N * j.Dp;
     const unsigned grid = (unsigned)ceil_div(n, THREADS);
+    const unsigned grid4 = (unsigned)ceil_div(n / 4, THREADS);
     void *W = h->ws.feat[0].p;
     const int32_t *perm = h->g.perm.as<int32_t>();
     const double *s64 = h->sc.s64.as<double>();
@@ -607,7 +673,7 @@ ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStre
     const int d = j.d;
 #define NOISE_CALL(T, D)                                                                        \
     (X ? (prep_x_kernel<T, D><<<grid, THREADS, 0, s>>>(N, d, X, perm, s64, (T *)W), IFGP_OK)    \
-       : (noise_kernel<T, D><<<grid, THREADS, 0, s>>>(N, d, seed, perm, s64, (T *)W), IFGP_OK))
+       : (noise_kernel<T, D><<<grid4, THREADS, 0, s>>>(N, d, seed, perm, s64, (T *)W), IFGP_OK))
     IFGP_DISPATCH(j.storage, j.Dp, NOISE_CALL);
 #undef NOISE_CALL
     set_error("unsupported storage/width");
@@ -624,7 +690,7 @@ ifgp_status launch_epilogue(ifgp_graph_s *h, hipStream_t s) {
     float *out = j.out;
     const int d = j.d;
 #define EPI_CALL(T, D)                                                                          \
-    (epilogue_kernel<T, D><<<(unsigned)ceil_div(N * Cfg<T, D>::LPR, THREADS), THREADS, 0, s>>>( \
+    (epilogue_kernel<T, D><<<(unsigned)ceil_div(N * (D / 4), THREADS), THREADS, 0, s>>>(        \
          N, d, W, node, ab, perm, out),                                                         \
      IFGP_OK)
     IFGP_DISPATCH(j.storage, j.Dp, EPI_CALL);
@@ -672,7 +738,7 @@ int64_t hop_blocks(const GraphData &g, int Dp, int storage) {
 
 ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
                                   hipStream_t s) {
-    const int64_t n = N * d;
+    const int64_t n = N * ((d + 3) / 4);
     if (n == 0) return IFGP_OK;
     const unsigned grid = (unsigned)ceil_div(n, THREADS);
     switch (dtype) {
@@ -697,7 +763,8 @@ ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s
     scales_kernel<<<grid, THREADS, 0, s>>>(g.N, g.irowptr.as<int64_t>(), tau, eps,
                                            sc.s64.as<double>());
     IFGP_LAUNCHED();
-    nodeinfo_kernel<<<grid, THREADS, 0, s>>>(g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
+    nodeinfo_kernel<<<(unsigned)ceil_div(g.N, THREADS / NI_LANES), THREADS, 0, s>>>(
+        g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
                                              sc.s64.as<double>(), tau, eps,
                                              sc.nodeinfo.as<float4>());
     IFGP_LAUNCHED();

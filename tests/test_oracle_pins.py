@@ -50,6 +50,28 @@ def test_philox_matches_numpy_library(seed):
         assert np.array_equal(cref.philox4x64_10([i + 1, c, 0, 0], seed, 0), ref)
 
 
+def test_gaussian_input_uses_all_four_words():
+    """Columns 4q..4q+3 of row i come from numpy's Philox block (i+1, q):
+    (cos, sin) of the Box-Muller pair on words 0-1, then on words 2-3."""
+    seed, d = 99, 12
+    X = ffp.gaussian_input(5, d, seed)
+    for i in range(5):
+        for q in range(d // 4):
+            bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                                  counter=np.array([i, q, 0, 0], dtype=np.uint64))
+            w = bg.random_raw(4)
+            u = ((w >> np.uint64(11)).astype(np.float64) + 0.5) / 2.0**53
+            for p_ in range(2):
+                r = np.sqrt(-2 * np.log(u[2 * p_]))
+                ang = 2 * np.pi * u[2 * p_ + 1]
+                assert X[i, 4 * q + 2 * p_] == r * np.cos(ang) / np.sqrt(d)
+                assert X[i, 4 * q + 2 * p_ + 1] == r * np.sin(ang) / np.sqrt(d)
+    # cos and sin halves of one pair are uncorrelated
+    Y = ffp.gaussian_input(20000, 4, 5)
+    assert abs(np.corrcoef(Y[:, 0], Y[:, 1])[0, 1]) < 0.03
+    assert abs(np.corrcoef(Y[:, 0], Y[:, 2])[0, 1]) < 0.03
+
+
 def test_gaussian_input_distribution():
     d = 16
     X = ffp.gaussian_input(4000, d, seed=7)
