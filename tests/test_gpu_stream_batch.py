@@ -1,0 +1,171 @@
+"""Streaming merge (Algorithm 2, topology merge and D_tau update) and batched
+embedding of several graphs, through the C ABI.
+
+After every increment the resident CSR must equal the canonical CSR of all
+edges so far, bit for bit, and the embedding must equal a from-scratch build
+and embed of the same edges bit for bit (the execution plan is a pure function
+of the canonical CSR).  A graph's embedding inside a batch must equal its
+embedding alone, bit for bit."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import cref, ffp  # noqa: E402
+from workloads import dcsbm, random_edges, shuffled_increments  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ifgp():
+    import torch
+    import paper_2508_19737_amd as m
+    assert torch.cuda.is_available()
+    m.use_torch_allocator()
+    return m
+
+
+def check_csr(G, src, dst, N):
+    rp, ci, loops, dups = ffp.canonical_csr(src, dst, N)
+    grp, gci, gdeg = G.export_csr()
+    assert np.array_equal(grp, rp)
+    assert np.array_equal(gci.astype(np.int64), ci)
+    assert np.array_equal(gdeg.astype(np.int64), np.diff(rp))
+    inf = G.info()
+    assert (inf["N"], inf["nnz"], inf["self_loops_dropped"], inf["dups_dropped"]) == \
+        (N, int(rp[-1]), loops, dups)
+    return rp, ci
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f32"])
+def test_emerging_edges_stream(ifgp, storage):
+    g = dcsbm(20_000, 30, seed=0)
+    incs = shuffled_increments(g, 10, seed=2)
+    # add duplicates and self-loops to some increments
+    s3, d3 = incs[3]
+    incs[3] = (np.concatenate([s3, s3[:50], [7, 9]]), np.concatenate([d3, d3[:50], [7, 9]]))
+    s6, d6 = incs[6]
+    incs[6] = (np.concatenate([s6, incs[1][1][:40]]), np.concatenate([d6, incs[1][0][:40]]))
+    G = ifgp.Graph(*incs[0], g.N)
+    src, dst = incs[0]
+    for t in range(1, 10):
+        G.stream_add(*incs[t])
+        src = np.concatenate([src, incs[t][0]])
+        dst = np.concatenate([dst, incs[t][1]])
+        rp, ci = check_csr(G, src, dst, g.N)
+        got = G.embed(-1.0, 8, 64, 1, storage=storage).cpu().numpy()
+        F = ifgp.Graph(src, dst, g.N)
+        fresh = F.embed(-1.0, 8, 64, 1, storage=storage).cpu().numpy()
+        F.destroy()
+        assert np.array_equal(got, fresh), t
+    ref = cref.ffp_from_input(rp, ci, g.N, -1.0, 8, ffp.gaussian_input(g.N, 64, 1))
+    tol = 1e-5 if storage == "f32" else 1e-2
+    assert ffp.rel_frobenius(got, ref) <= tol
+    G.destroy()
+
+
+def test_snowball_stream_adds_nodes(ifgp):
+    """new_N > N: nodes arrive with their edges (the snowball model)."""
+    g = dcsbm(6000, 12, seed=3)
+    order = np.argsort(np.random.default_rng(0).permutation(g.N))   # arrival rank of each node
+    cut = [0, 2000, 4000, 6000]
+    # relabel so that nodes arrive in id order
+    src, dst = order[g.src], order[g.dst]
+    G = None
+    for t in range(1, 4):
+        n_t = cut[t]
+        keep = (np.maximum(src, dst) < n_t) & (np.maximum(src, dst) >= cut[t - 1])
+        if G is None:
+            G = ifgp.Graph(src[keep], dst[keep], n_t)
+        else:
+            G.stream_add(src[keep], dst[keep], new_N=n_t)
+        cum = np.maximum(src, dst) < n_t
+        check_csr(G, src[cum], dst[cum], n_t)
+        got = G.embed(-1.0, 4, 32, 5).cpu().numpy()
+        F = ifgp.Graph(src[cum], dst[cum], n_t)
+        assert np.array_equal(got, F.embed(-1.0, 4, 32, 5).cpu().numpy())
+        F.destroy()
+    G.destroy()
+
+
+def test_stream_add_strong_guarantee(ifgp):
+    src, dst = random_edges(500, 3000, 8)
+    G = ifgp.Graph(src, dst, 500)
+    before = G.export_csr()
+    emb = G.embed(-1.0, 4, 16, 2).cpu().numpy()
+    with pytest.raises(ifgp.IfgpError) as e:
+        G.stream_add(np.array([1, 2, 500]), np.array([3, 4, 5]))
+    assert e.value.status == -2
+    with pytest.raises(ifgp.IfgpError) as e:
+        G.stream_add(np.array([1]), np.array([2]), new_N=499)
+    assert e.value.status == -1
+    after = G.export_csr()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    assert np.array_equal(G.embed(-1.0, 4, 16, 2).cpu().numpy(), emb)
+    G.stream_add(np.zeros(0, np.int64), np.zeros(0, np.int64))   # empty increment
+    assert all(np.array_equal(a, b) for a, b in zip(before, G.export_csr()))
+    G.destroy()
+
+
+def graph_mix(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        N = int(np.exp(rng.uniform(np.log(500), np.log(30_000))))
+        B = max(2, round(N ** 0.33))
+        g = dcsbm(N, B, mean_deg=float(rng.uniform(10, 30)), ratio=float(rng.uniform(2, 5)),
+                  seed=seed * 100 + k)
+        out.append((g, int(rng.choice([32, 64]))))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f32"])
+def test_batch_equals_alone(ifgp, storage):
+    mix = graph_mix(1, 7)
+    graphs = [ifgp.Graph(g.src, g.dst, g.N) for g, _ in mix]
+    ds = [d for _, d in mix]
+    Ks = [8, 8, 3, 8, 0, 5, 8]
+    taus = [-1.0, -1.5, 0.0, -1.0, -1.0, 2.0, -1.0]
+    seeds = list(range(7))
+    outs = ifgp.embed_batch(graphs, taus, Ks, ds, seeds, storage=storage)
+    for G, o, t, K, d, sd in zip(graphs, outs, taus, Ks, ds, seeds):
+        alone = G.embed(t, K, d, sd, storage=storage)
+        assert np.array_equal(o.cpu().numpy(), alone.cpu().numpy())
+    # and one graph against the oracle
+    g0, d0 = mix[0]
+    rp, ci, _, _ = ffp.canonical_csr(g0.src, g0.dst, g0.N)
+    ref = ffp.ffp_from_input(rp, ci, g0.N, -1.0, 8, ffp.gaussian_input(g0.N, d0, 0))
+    assert ffp.rel_frobenius(outs[0].cpu().numpy(), ref) <= (1e-5 if storage == "f32" else 1e-2)
+    for G in graphs:
+        G.destroy()
+
+
+def test_jobs_admitted_between_hops(ifgp):
+    """Continuous batching: graphs join the running set at hop boundaries and
+    each result equals the graph embedded alone."""
+    mix = graph_mix(2, 5)
+    graphs = [ifgp.Graph(g.src, g.dst, g.N) for g, _ in mix]
+    ds = [d for _, d in mix]
+    outs = [None] * 5
+    active = []
+    schedule = {0: [0, 1], 2: [2], 3: [3, 4]}   # step -> graphs admitted before that step
+    done = set()
+    step = 0
+    while len(done) < 5:
+        for k in schedule.get(step, []):
+            outs[k] = graphs[k].job_begin(-1.0, 8, ds[k], 10 + k, storage="bf16")
+            active.append(k)
+        flags = ifgp.job_step([graphs[k] for k in active])
+        for k, f in zip(list(active), flags):
+            if f:
+                done.add(k)
+                active.remove(k)
+        step += 1
+        assert step < 100
+    for k in range(5):
+        alone = graphs[k].embed(-1.0, 8, ds[k], 10 + k, storage="bf16")
+        assert np.array_equal(outs[k].cpu().numpy(), alone.cpu().numpy())
+    with pytest.raises(ifgp.IfgpError) as e:
+        ifgp.job_step([graphs[0]])
+    assert e.value.status == -5
+    for G in graphs:
+        G.destroy()
