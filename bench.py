@@ -74,6 +74,85 @@ def cpu_baseline(g, rp, ci, tau, K, d, cols):
                       f"columns of the same graph; {t:.1f} s; host CPU: {cpu_info()}"}
 
 
+def bench_streaming(ifgp, say, reps=20):
+    """Emerging-edge stream: DC-SBM N=200,000, 100 blocks, mean degree 20;
+    edges shuffled (seed 2) into 10 equal increments arriving in order; after
+    each increment the resident graph is merged (ifgp_stream_add) and
+    re-embedded (d=64, tau=-1, K=8, BF16).  Latency per increment, with the
+    increment already in device memory."""
+    import torch
+    from workloads import dcsbm, shuffled_increments
+    say("streaming: N=200000, 10 increments")
+    g = dcsbm(200_000, 100, mean_deg=20.0, ratio=2.5, seed=0)
+    incs = [(torch.as_tensor(s, device="cuda"), torch.as_tensor(t, device="cuda"))
+            for s, t in shuffled_increments(g, 10, seed=2)]
+    out = torch.empty((g.N, 64), dtype=torch.float32, device="cuda")
+    empty = torch.zeros(0, dtype=torch.int64, device="cuda")
+    lat = []
+    for rep in range(reps + 1):
+        G = ifgp.Graph(empty, empty, g.N)
+        torch.cuda.synchronize()
+        for s, t in incs:
+            t0 = time.perf_counter()
+            G.stream_add(s, t)
+            G.embed(-1.0, 8, 64, 1, out=out, storage="bf16")
+            torch.cuda.synchronize()
+            if rep > 0:               # the first pass is warmup
+                lat.append((time.perf_counter() - t0) * 1e3)
+        G.destroy()
+    lat = np.array(lat)
+    return {"workload": "DC-SBM N=200000 B=100 mean degree 20, 10 shuffled edge increments "
+                        "(seed 2), stream_add + re-embed d=64 tau=-1 K=8 bf16, device-resident "
+                        "increments",
+            "samples": int(lat.size), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "per_increment_mean_ms": [float(x) for x in lat.reshape(reps, 10).mean(axis=0)]}
+
+
+def bench_serving(a, say):
+    """Serving mix: requests draw DC-SBM graphs (N log-uniform in [1e3, 5e5],
+    blocks ~ N^0.33, mean degree U[10,30], ratio U[2,5]) from a seeded pool;
+    d in {32, 64}, tau=-1, K=8.  The Poisson rate is 0.7 x the measured
+    capacity of the plain FP32 one-at-a-time path.  Batched BF16 continuous
+    batching vs FP32 one-at-a-time on the same arrivals, plus a closed loop
+    (every request queued at t=0) for peak graphs/s."""
+    from paper_2508_19737_amd import serve
+    from workloads.serving import graph_pool, request_stream
+    say(f"serving: pool of {a.serve_pool} graphs, {a.serve_requests} requests")
+    pool = graph_pool(pool=a.serve_pool, n_min=1000, n_max=500_000, seed=3)
+
+    def reqs(rate, storage, n):
+        return [serve.Request(rid=i, arrival=x["arrival"], src=x["graph"].src, dst=x["graph"].dst,
+                              N=x["graph"].N, tau=-1.0, K=8, d=x["d"], seed=x["seed"],
+                              storage=storage)
+                for i, x in enumerate(request_stream(pool, n, rate, seed=3))]
+
+    n = a.serve_requests
+    serve.sequential(reqs(float("inf"), "f32", 20), keep_outputs=False)          # warmup
+    cal = serve.summarize(serve.sequential(reqs(float("inf"), "f32", min(200, n)),
+                                           keep_outputs=False))
+    rate = 0.7 * cal["graphs_per_s"]
+    say(f"serving: FP32 one-at-a-time capacity {cal['graphs_per_s']:.1f}/s, rate {rate:.1f}/s")
+    srv = serve.Server(max_slots=64)
+    srv.run(reqs(float("inf"), "bf16", 20), keep_outputs=False)                    # warmup
+    batched = serve.summarize(srv.run(reqs(rate, "bf16", n), keep_outputs=False, progress=say))
+    say(f"serving: batched {batched}")
+    closed_b = serve.summarize(srv.run(reqs(float("inf"), "bf16", n), keep_outputs=False,
+                                       progress=say))
+    say(f"serving: closed loop batched {closed_b}")
+    srv.close()
+    seq = serve.summarize(serve.sequential(reqs(rate, "f32", n), keep_outputs=False))
+    say(f"serving: one at a time {seq}")
+    closed_s = serve.summarize(serve.sequential(reqs(float("inf"), "f32", n), keep_outputs=False))
+    sizes = [g.N for g in pool]
+    return {"workload": f"{n} requests, Poisson rate {rate:.1f}/s (0.7 x FP32 one-at-a-time "
+                        f"capacity), graphs from a seeded pool of {len(pool)} DC-SBM graphs with "
+                        f"N {min(sizes)}..{max(sizes)}, d in {{32,64}}, tau=-1, K=8",
+            "rate_per_s": rate,
+            "batched_bf16": batched, "one_at_a_time_fp32": seq,
+            "closed_loop_batched_bf16": closed_b, "closed_loop_one_at_a_time_fp32": closed_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +166,10 @@ def main():
     ap.add_argument("--tau", type=float, default=-1.0)
     ap.add_argument("--cpu-cols", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reads 1 GiB, writes 1 GiB) so "
                          "that profiler byte counters can be scaled against known traffic")
@@ -105,7 +188,8 @@ def main():
         print(m, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    ifgp.use_torch_allocator()
+    # library buffers: the device's stream-ordered pool (the library default)
+    ifgp.use_hip_allocator()
     if a.calibrate:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -178,6 +262,10 @@ def main():
     for x in graphs:
         x.destroy()
 
+    del graphs, G
+    streaming = None if a.no_streaming else bench_streaming(ifgp, say)
+    serving = None if a.no_serving else bench_serving(a, say)
+
     work = nnz * a.d * a.K
     rec = {
         "metric": "FFP embed throughput (nnz*d*K/s)",
@@ -204,6 +292,8 @@ def main():
                      "launch_ms": hop_ms_avg, "model": "no gathered row reused from cache",
                      "achieved_compulsory": comp},
         "cpu_baseline": cpu,
+        "streaming": streaming,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

@@ -31,8 +31,12 @@
  *     once that stream is synchronised; calls that must learn a size (graph
  *     build, stream_add, export) synchronise it themselves.
  *   - A graph handle owns all device memory it allocated (through the
- *     allocator hook, see ifgp_set_allocator).  A handle is not thread-safe;
- *     distinct handles may be used from distinct threads.
+ *     allocator hook, see ifgp_set_allocator; by default the library's
+ *     caching allocator) and releases it stream-ordered on the stream each
+ *     block was allocated on.  Work that uses a handle on other
+ *     streams must be complete before ifgp_stream_add or ifgp_destroy on it.
+ *     A handle is not thread-safe; distinct handles may be used from
+ *     distinct threads.
  *   - Node ids are 0 .. N-1 and N must be below 2^31 - 1.
  */
 #ifndef IFGP_H
@@ -202,14 +206,21 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
                                  int64_t *bytes);
 
 /*
- * Route every device allocation of the library through alloc/free (both
- * non-NULL), or back to hipMalloc/hipFree (both NULL).  alloc(bytes, stream,
+ * Route every later device allocation of the library through alloc/free
+ * (both non-NULL), or back to the library's caching allocator (both NULL):
+ * hipMalloc'd blocks kept per (device, stream) after release and reused only
+ * by later allocations on the same stream.  Each block is released through
+ * the allocator that produced it, so the hook may change at any time.  alloc(bytes, stream,
  * ctx) returns device memory usable on `stream` or NULL; free(ptr, stream,
- * ctx) releases it.  Process-wide; set it before creating handles and keep the
- * callbacks alive while any handle exists.
+ * ctx) releases it.  Process-wide; keep the callbacks alive while any block
+ * they produced exists.
  */
 IFGP_API ifgp_status ifgp_set_allocator(void *(*alloc)(size_t, void *, void *),
                                void (*free_fn)(void *, void *, void *), void *ctx);
+
+/* Return the cached free blocks of the library's own allocator to the device
+ * (hipFree; synchronises the device).  Blocks in use are not affected. */
+IFGP_API ifgp_status ifgp_empty_cache(void);
 
 /*
  * Kernel timing: while enabled on a handle, each hop launch of that handle is

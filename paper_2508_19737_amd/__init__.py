@@ -10,7 +10,7 @@ Public API (thin wrappers over the C ABI in include/ifgp.h):
     gaussian_input(N, d, seed)    the random input alone
 """
 from ._lib import (BF16, F16, F32, F64, EXPORTS, Graph, IfgpError, embed_batch,  # noqa: F401
-                   footprint_bytes, gaussian_input, job_step, lib, params, use_hip_allocator,
+                   empty_cache, footprint_bytes, gaussian_input, job_step, lib, params, use_hip_allocator,
                    use_torch_allocator, version)
 
 from ._lib import LIB_PATH  # noqa: E402,F401

@@ -25,7 +25,8 @@ EXPORTS = [
     "ifgp_default_params", "ifgp_build_graph", "ifgp_embed", "ifgp_embed_x",
     "ifgp_gaussian_input", "ifgp_stream_add", "ifgp_embed_batch", "ifgp_job_begin",
     "ifgp_job_step", "ifgp_graph_info", "ifgp_export_csr", "ifgp_export_scales",
-    "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_timing_enable", "ifgp_timing_read",
+    "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_empty_cache", "ifgp_timing_enable",
+    "ifgp_timing_read",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
 ]
 
@@ -44,6 +45,10 @@ class IfgpError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python paper_2508_19737_amd/build.py`")
+    # torch ships its own HIP runtime.  Load it first so that libifgp binds to
+    # that same runtime (same soname) instead of a second copy from /opt/rocm:
+    # two HIP runtimes in one process do not share the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, i64, i32, u64, f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                              ctypes.c_double)
@@ -63,6 +68,7 @@ def _load():
         "ifgp_export_scales": [P, f64, f64, P],
         "ifgp_footprint_bytes": [i64, i64, i32, i32, P],
         "ifgp_set_allocator": [P, P, P],
+        "ifgp_empty_cache": [],
         "ifgp_timing_enable": [P, ctypes.c_int],
         "ifgp_timing_read": [P, P, P],
         "ifgp_destroy": [P],
@@ -147,9 +153,15 @@ def use_torch_allocator():
 
 
 def use_hip_allocator():
+    """Back to the library's own caching allocator (the default)."""
     global _hooks
     check(lib.ifgp_set_allocator(None, None, None))
     _hooks = None
+
+
+def empty_cache():
+    """Return the library allocator's cached blocks to the device."""
+    check(lib.ifgp_empty_cache())
 
 
 def _edges(src, dst):

@@ -4,7 +4,10 @@
 // primitives.hip or ffp.hip.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -29,26 +32,103 @@ void set_error(const char *fmt, ...) {
     g_last_error = buf;
 }
 
-void *raw_alloc(size_t bytes, hipStream_t s) {
-    if (g_hook.alloc) return g_hook.alloc(bytes, (void *)s, g_hook.ctx);
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
+namespace {
+// Default allocator: a caching allocator over hipMalloc.  Freed blocks are
+// kept per (device, stream) and handed out again only to allocations on the
+// same stream, which are ordered after every earlier use of the block on that
+// stream (the release is stream-ordered, as with torch's caching allocator).
+// A request reuses the smallest cached block of at least its size and at most
+// twice its size; when hipMalloc fails, the whole cache is released and the
+// allocation retried.
+class BlockCache {
+  public:
+    void *get(size_t bytes, hipStream_t s) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto &fl = free_[{dev, s}];
+            auto it = fl.lower_bound(bytes);
+            if (it != fl.end() && it->first <= 2 * bytes) {
+                void *p = it->second;
+                fl.erase(it);
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            release_all();
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        size_[p] = bytes;
+        return p;
     }
+    void put(void *p, hipStream_t s) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(mu_);
+        free_[{dev, s}].insert({size_[p], p});
+    }
+    // hipFree every cached block (implicitly synchronises the device).
+    void release_all() {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto &kv : free_)
+            for (auto &blk : kv.second) {
+                (void)hipFree(blk.second);
+                size_.erase(blk.second);
+            }
+        free_.clear();
+    }
+
+  private:
+    std::mutex mu_;
+    std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_;
+    std::unordered_map<void *, size_t> size_;
+};
+
+BlockCache &cache() {
+    static BlockCache *c = new BlockCache();  // never destroyed: outlives static handles
+    return *c;
+}
+
+void cache_free(void *p, void *stream, void *) { cache().put(p, (hipStream_t)stream); }
+
+// Size classes: 512-byte steps below 1 MiB, 2 MiB steps above.
+size_t size_class(size_t n) {
+    const size_t step = n < (1u << 20) ? 512 : (2u << 20);
+    return (n + step - 1) / step * step;
+}
+}  // namespace
+
+void release_cached_blocks() { cache().release_all(); }
+
+void *raw_alloc(size_t bytes, hipStream_t s, FreeFn *free_fn, void **ctx) {
+    if (g_hook.alloc) {
+        *free_fn = g_hook.free;
+        *ctx = g_hook.ctx;
+        return g_hook.alloc(bytes, (void *)s, g_hook.ctx);
+    }
+    void *p = cache().get(size_class(bytes), s);
+    *free_fn = cache_free;
+    *ctx = nullptr;
     return p;
 }
 
-void raw_free(void *p, hipStream_t s) {
-    if (!p) return;
-    if (g_hook.free) g_hook.free(p, (void *)s, g_hook.ctx);
-    else (void)hipFree(p);
+void raw_free(void *p, hipStream_t s, FreeFn free_fn, void *ctx) {
+    if (p && free_fn) free_fn(p, (void *)s, ctx);
 }
 
 ifgp_status alloc(Buf &b, size_t bytes, hipStream_t s) {
     b.reset();
     const size_t n = bytes < 256 ? 256 : ((bytes + 255) / 256) * 256;
-    void *p = raw_alloc(n, s);
+    FreeFn fn = nullptr;
+    void *ctx = nullptr;
+    void *p = raw_alloc(n, s, &fn, &ctx);
     if (!p) {
         set_error("device allocation of %zu bytes failed", n);
         return IFGP_E_OOM;
@@ -56,6 +136,8 @@ ifgp_status alloc(Buf &b, size_t bytes, hipStream_t s) {
     b.p = p;
     b.bytes = n;
     b.s = s;
+    b.free_fn = fn;
+    b.ctx = ctx;
     return IFGP_OK;
 }
 
@@ -148,8 +230,9 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
         delete h;
         return st;
     };
-    if (hipGetDevice(&h->device) != hipSuccess) {
-        set_error("no HIP device");
+    const hipError_t de = hipGetDevice(&h->device);
+    if (de != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(de));
         return fail(IFGP_E_DEVICE);
     }
     h->stream = s;
@@ -366,6 +449,11 @@ IFGP_API ifgp_status ifgp_set_allocator(void *(*alloc_fn)(size_t, void *, void *
     g_hook.alloc = alloc_fn;
     g_hook.free = free_fn;
     g_hook.ctx = alloc_fn ? ctx : nullptr;
+    return IFGP_OK;
+}
+
+IFGP_API ifgp_status ifgp_empty_cache(void) {
+    release_cached_blocks();
     return IFGP_OK;
 }
 

@@ -37,14 +37,20 @@ void set_error(const char *fmt, ...);
 #define IFGP_LAUNCHED() IFGP_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------- memory
-void *raw_alloc(size_t bytes, hipStream_t s);
-void raw_free(void *p, hipStream_t s);
+// Release function of the allocator that produced a block: every buffer frees
+// through the allocator it came from, even if the hook changes meanwhile.
+using FreeFn = void (*)(void *, void *, void *);
+void *raw_alloc(size_t bytes, hipStream_t s, FreeFn *free_fn, void **ctx);
+void raw_free(void *p, hipStream_t s, FreeFn free_fn, void *ctx);
 
-// Owning device buffer; memory comes from the allocator hook.
+// Owning device buffer; memory comes from the allocator hook (default: the
+// device's stream-ordered memory pool).
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
     hipStream_t s = nullptr;
+    FreeFn free_fn = nullptr;
+    void *ctx = nullptr;
 
     Buf() = default;
     Buf(const Buf &) = delete;
@@ -63,11 +69,15 @@ struct Buf {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
         std::swap(s, o.s);
+        std::swap(free_fn, o.free_fn);
+        std::swap(ctx, o.ctx);
     }
     void reset() {
-        if (p) raw_free(p, s);
+        if (p) raw_free(p, s, free_fn, ctx);
         p = nullptr;
         bytes = 0;
+        free_fn = nullptr;
+        ctx = nullptr;
     }
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };

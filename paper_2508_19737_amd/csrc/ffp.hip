@@ -26,6 +26,7 @@
 // Heavy rows come first in the grid, so long blocks start early.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -446,19 +447,23 @@ __global__ __launch_bounds__(THREADS) void hop_kernel(const HopArgs a) {
     hop_block<T, D>(a, blockIdx.x);
 }
 
-// Many graphs in one launch: graph gi owns blocks [blk_start[gi], blk_start[gi+1]).
+// Many graphs in one launch; the table travels as a kernel argument (no
+// device allocation, no host synchronisation).  Graph gi owns blocks
+// [start[gi], start[gi+1]).
+constexpr int MAX_BATCH = 24;
+struct HopBatch {
+    HopArgs a[MAX_BATCH];
+    int64_t start[MAX_BATCH + 1];
+    int n;
+};
+static_assert(sizeof(HopBatch) <= 3584, "batch table must fit the kernel argument segment");
+
 template <typename T, int D>
-__global__ __launch_bounds__(THREADS) void hop_batch_kernel(const HopArgs *__restrict__ args,
-                                                            const int64_t *__restrict__ blk_start,
-                                                            int ngraphs) {
+__global__ __launch_bounds__(THREADS) void hop_batch_kernel(const HopBatch bt) {
     const int64_t b = blockIdx.x;
-    int lo = 0, hi = ngraphs - 1;
-    while (lo < hi) {  // last gi with blk_start[gi] <= b
-        const int mid = (lo + hi + 1) >> 1;
-        if (blk_start[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    hop_block<T, D>(args[lo], b - blk_start[lo]);
+    int gi = 0;
+    while (gi + 1 < bt.n && bt.start[gi + 1] <= b) ++gi;
+    hop_block<T, D>(bt.a[gi], b - bt.start[gi]);
 }
 
 // mu, sigma per column from the block partials (fixed order), then
@@ -518,9 +523,14 @@ __global__ __launch_bounds__(THREADS) void finalize_kernel(const FinArgs f) {
     finalize_column(f, blockIdx.x);
 }
 
+struct FinBatch {
+    FinArgs f[MAX_BATCH];
+};
+static_assert(sizeof(FinBatch) <= 3584, "batch table must fit the kernel argument segment");
+
 // grid = (D, graphs)
-__global__ __launch_bounds__(THREADS) void finalize_batch_kernel(const FinArgs *__restrict__ fs) {
-    const FinArgs f = fs[blockIdx.y];
+__global__ __launch_bounds__(THREADS) void finalize_batch_kernel(const FinBatch fb) {
+    const FinArgs &f = fb.f[blockIdx.y];
     if ((int)blockIdx.x < f.D) finalize_column(f, blockIdx.x);
 }
 
@@ -649,12 +659,9 @@ ifgp_status launch_hop(const HopArgs &a, int storage, int Dp, hipStream_t s) {
     return IFGP_E_INVALID;
 }
 
-ifgp_status launch_hop_batch(const HopArgs *args_dev, const int64_t *blk_start_dev, int n,
-                             int64_t total_blocks, int storage, int Dp, hipStream_t s) {
-#define HOPB_CALL(T, D)                                                                         \
-    (hop_batch_kernel<T, D><<<(unsigned)total_blocks, THREADS, 0, s>>>(args_dev, blk_start_dev, \
-                                                                       n),                      \
-     IFGP_OK)
+ifgp_status launch_hop_batch(const HopBatch &bt, int64_t total_blocks, int storage, int Dp,
+                             hipStream_t s) {
+#define HOPB_CALL(T, D) (hop_batch_kernel<T, D><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt), IFGP_OK)
     IFGP_DISPATCH(storage, Dp, HOPB_CALL);
 #undef HOPB_CALL
     set_error("unsupported storage/width");
@@ -863,37 +870,24 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
             IFGP_LAUNCHED();
         } else {
             const int m = (int)G.members.size();
-            std::vector<HopArgs> ha(m);
-            std::vector<FinArgs> fa(m);
-            std::vector<int64_t> start(m + 1, 0);
-            for (int i = 0; i < m; ++i) {
-                ha[i] = make_hop_args(G.members[i]);
-                fa[i] = make_fin_args(G.members[i]);
-                start[i + 1] = start[i] + ha[i].blocks;
+            for (int b0 = 0; b0 < m; b0 += MAX_BATCH) {
+                const int nb = std::min(MAX_BATCH, m - b0);
+                HopBatch bt{};
+                FinBatch fb{};
+                bt.n = nb;
+                bt.start[0] = 0;
+                for (int i = 0; i < nb; ++i) {
+                    bt.a[i] = make_hop_args(G.members[b0 + i]);
+                    fb.f[i] = make_fin_args(G.members[b0 + i]);
+                    bt.start[i + 1] = bt.start[i] + bt.a[i].blocks;
+                }
+                for (int i = 0; i < nb; ++i) IFGP_TRY(record_event(G.members[b0 + i], s, true));
+                IFGP_TRY(launch_hop_batch(bt, bt.start[nb], G.storage, G.Dp, s));
+                IFGP_LAUNCHED();
+                for (int i = 0; i < nb; ++i) IFGP_TRY(record_event(G.members[b0 + i], s, false));
+                finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)nb), THREADS, 0, s>>>(fb);
+                IFGP_LAUNCHED();
             }
-            // argument tables: staged through the first member's stream-ordered scratch
-            Buf tab;
-            const size_t bytes = sizeof(HopArgs) * m + sizeof(FinArgs) * m + sizeof(int64_t) * (m + 1);
-            IFGP_TRY(alloc(tab, bytes, s));
-            std::vector<char> host(bytes);
-            std::memcpy(host.data(), ha.data(), sizeof(HopArgs) * m);
-            std::memcpy(host.data() + sizeof(HopArgs) * m, fa.data(), sizeof(FinArgs) * m);
-            std::memcpy(host.data() + (sizeof(HopArgs) + sizeof(FinArgs)) * m, start.data(),
-                   sizeof(int64_t) * (m + 1));
-            IFGP_HIP(hipMemcpyAsync(tab.p, host.data(), bytes, hipMemcpyHostToDevice, s));
-            const HopArgs *ha_d = tab.as<HopArgs>();
-            const FinArgs *fa_d = (const FinArgs *)((char *)tab.p + sizeof(HopArgs) * m);
-            const int64_t *st_d =
-                (const int64_t *)((char *)tab.p + (sizeof(HopArgs) + sizeof(FinArgs)) * m);
-            for (auto *h : G.members) IFGP_TRY(record_event(h, s, true));
-            IFGP_TRY(launch_hop_batch(ha_d, st_d, m, start[m], G.storage, G.Dp, s));
-            IFGP_LAUNCHED();
-            for (auto *h : G.members) IFGP_TRY(record_event(h, s, false));
-            finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)m), THREADS, 0, s>>>(fa_d);
-            IFGP_LAUNCHED();
-            // the pageable copy above completed before returning; `tab` is
-            // released stream-ordered by the allocator hook
-            IFGP_HIP(hipStreamSynchronize(s));
         }
         for (auto *h : G.members) {
             Job &j = h->job;

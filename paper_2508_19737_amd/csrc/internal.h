@@ -80,6 +80,9 @@ struct ifgp_graph_s {
 
 namespace ifgp {
 
+// ---- api.hip
+void release_cached_blocks();
+
 // ---- graph.hip
 // Build the canonical CSR and plan from edges already in device memory.
 ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
