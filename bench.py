@@ -47,6 +47,31 @@ def hop_blocks(N, deg):
     return hub + -(-med // 4) + -(-(N - hub - med) // 256)
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hop_kernel_dcsbm2M_bf16_d64_counters.md")
+KERNEL_SOURCES = ["paper_2508_19737_amd/csrc/ffp.hip", "paper_2508_19737_amd/csrc/internal.h",
+                  "paper_2508_19737_amd/csrc/common.h"]
+
+
+def measured_traffic(workload_matches):
+    """HBM-side bytes per hop launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a 1 GiB copy), or None
+    when the workload differs or the hop kernel's sources changed since."""
+    import hashlib
+    if not workload_matches or not os.path.exists(COUNTER_SUMMARY):
+        return None
+    kv = {}
+    for line in open(COUNTER_SUMMARY):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            kv[k] = v
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_info():
     model = platform.processor() or "unknown"
     try:
@@ -287,7 +312,9 @@ def main():
         "embed_only": {"ms": t_embed * 1e3, "value": work / t_embed,
                        "build_ms": (t_step - t_embed) * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic((a.N, a.d, a.K, a.storage, a.blocks) ==
+                                                 (2_000_000, 64, 8, "bf16", 200)),
                      "kernel": "hop_kernel", "bytes_per_launch": bytes_hop,
                      "launch_ms": hop_ms_avg, "model": "no gathered row reused from cache",
                      "achieved_compulsory": comp},
