@@ -429,8 +429,8 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
     const int64_t Dp = padded_width(d);
     // resident graph: canonical CSR + degrees + plan (perm, iperm, relabelled CSR)
     int64_t total = 2 * (8 * (N + 1) + 4 * nnz) + 4 * N * 3;
-    // scales: FP64 s and (s, sqrt(D_tau), r, 0) as float4
-    total += 8 * N + 16 * N;
+    // scales: FP64 s, FP32 s and (s, sqrt(D_tau), r, 0) as float4
+    total += 8 * N + 4 * N + 16 * N;
     // two feature buffers, block statistics (bounded by the row classes:
     // hub rows <= nnz / HUB_DEGREE, medium rows <= nnz / MED_DEGREE), coefficients
     const int64_t blocks = nnz / HUB_DEGREE + ceil_div(nnz / MED_DEGREE, MED_ROWS_PER_BLOCK) +
@@ -497,7 +497,11 @@ IFGP_API ifgp_status ifgp_destroy(ifgp_graph_t g) {
         if (pr.first) (void)hipEventDestroy(pr.first);
         if (pr.second) (void)hipEventDestroy(pr.second);
     }
+    hipStream_t aux = g->aux;
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    if (g->ev_join) (void)hipEventDestroy(g->ev_join);
     delete g;
+    if (aux) (void)hipStreamDestroy(aux);
     return IFGP_OK;
 }
 

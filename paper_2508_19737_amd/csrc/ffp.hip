@@ -219,20 +219,24 @@ __device__ __forceinline__ double dtau_of(double deg, double tau, double eps) {
 }
 
 __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, double tau,
-                              double eps, double *__restrict__ s64) {
+                              double eps, double *__restrict__ s64, float *__restrict__ s32) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
-    s64[k] = 1.0 / sqrt(dt);
+    const double sk = 1.0 / sqrt(dt);
+    s64[k] = sk;
+    s32[k] = (float)sk;
 }
 
-// 16 lanes per row: r_k = sum of s over the row's neighbours, lanes take
-// strided entries and combine by a fixed butterfly (deterministic order).
+// 16 lanes per row: r_k = sum of s over the row's neighbours (FP32 copies of
+// s gathered, summed in FP64), lanes take strided entries and combine by a
+// fixed butterfly (deterministic order).
 constexpr int NI_LANES = 16;
 __global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N,
                                                            const int64_t *__restrict__ irowptr,
                                                            const int32_t *__restrict__ icolidx,
                                                            const double *__restrict__ s64,
+                                                           const float *__restrict__ s32,
                                                            double tau, double eps,
                                                            float4 *__restrict__ info) {
     const int64_t k = (int64_t)blockIdx.x * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N,
     if (live) {
         beg = irowptr[k];
         end = irowptr[k + 1];
-        for (int64_t e = beg + l; e < end; e += NI_LANES) r += s64[icolidx[e]];
+        for (int64_t e = beg + l; e < end; e += NI_LANES) r += (double)s32[icolidx[e]];
     }
 #pragma unroll
     for (int off = NI_LANES / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, NI_LANES);
@@ -759,26 +763,51 @@ ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t d
     return IFGP_OK;
 }
 
-ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
+namespace {
+// s in FP64 and FP32 (cheap); node info (the neighbour sums r) follows.
+ifgp_status launch_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
     Scales &sc = h->sc;
-    if (sc.valid && sc.tau == tau && sc.eps == eps) return IFGP_OK;
-    sc.valid = false;
     const GraphData &g = h->g;
+    sc.valid = false;
     IFGP_TRY(ensure(sc.s64, sizeof(double) * g.N, s));
+    IFGP_TRY(ensure(sc.s32, sizeof(float) * g.N, s));
     IFGP_TRY(ensure(sc.nodeinfo, sizeof(float4) * g.N, s));
-    const unsigned grid = (unsigned)ceil_div(g.N, THREADS);
-    scales_kernel<<<grid, THREADS, 0, s>>>(g.N, g.irowptr.as<int64_t>(), tau, eps,
-                                           sc.s64.as<double>());
+    scales_kernel<<<(unsigned)ceil_div(g.N, THREADS), THREADS, 0, s>>>(
+        g.N, g.irowptr.as<int64_t>(), tau, eps, sc.s64.as<double>(), sc.s32.as<float>());
     IFGP_LAUNCHED();
+    return IFGP_OK;
+}
+
+ifgp_status launch_nodeinfo(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
+    Scales &sc = h->sc;
+    const GraphData &g = h->g;
     nodeinfo_kernel<<<(unsigned)ceil_div(g.N, THREADS / NI_LANES), THREADS, 0, s>>>(
-        g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
-                                             sc.s64.as<double>(), tau, eps,
-                                             sc.nodeinfo.as<float4>());
+        g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(), sc.s64.as<double>(),
+        sc.s32.as<float>(), tau, eps, sc.nodeinfo.as<float4>());
     IFGP_LAUNCHED();
     sc.tau = tau;
     sc.eps = eps;
     sc.valid = true;
     return IFGP_OK;
+}
+
+bool scales_cached(const ifgp_graph_s *h, double tau, double eps) {
+    return h->sc.valid && h->sc.tau == tau && h->sc.eps == eps;
+}
+
+// The library-owned stream and events used to overlap independent kernels.
+ifgp_status ensure_aux(ifgp_graph_s *h) {
+    if (!h->aux) IFGP_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    if (!h->ev_fork) IFGP_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    if (!h->ev_join) IFGP_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    return IFGP_OK;
+}
+}  // namespace
+
+ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
+    if (scales_cached(h, tau, eps)) return IFGP_OK;
+    IFGP_TRY(launch_scales(h, tau, eps, s));
+    return launch_nodeinfo(h, tau, eps, s);
 }
 
 ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s) {
@@ -806,7 +835,8 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
     }
     const int Dp = padded_width(d);
     h->job = Job{};
-    IFGP_TRY(ensure_scales(h, tau, p.eps, s));
+    const bool fresh_scales = !scales_cached(h, tau, p.eps);
+    if (fresh_scales) IFGP_TRY(launch_scales(h, tau, p.eps, s));
     const GraphData &g = h->g;
     const size_t fb = (size_t)g.N * Dp * dtype_bytes(p.storage);
     IFGP_TRY(ensure(h->ws.feat[0], fb, s));
@@ -824,8 +854,22 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
     j.ddof = p.znorm_ddof;
     j.cur = 0;
     j.out = out;
-    IFGP_TRY(launch_noise(h, seed, X, s));
-    IFGP_LAUNCHED();
+    if (fresh_scales && !X) {
+        // The random input needs only s; it is arithmetic-bound while the
+        // neighbour sums are gather-bound, so run them side by side.
+        IFGP_TRY(ensure_aux(h));
+        IFGP_HIP(hipEventRecord(h->ev_fork, s));
+        IFGP_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+        IFGP_TRY(launch_noise(h, seed, X, h->aux));
+        IFGP_LAUNCHED();
+        IFGP_HIP(hipEventRecord(h->ev_join, h->aux));
+        IFGP_TRY(launch_nodeinfo(h, tau, p.eps, s));
+        IFGP_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
+    } else {
+        if (fresh_scales) IFGP_TRY(launch_nodeinfo(h, tau, p.eps, s));
+        IFGP_TRY(launch_noise(h, seed, X, s));
+        IFGP_LAUNCHED();
+    }
     ab_identity_kernel<<<1, THREADS, 0, s>>>(h->ws.ab.as<float>(), Dp);
     IFGP_LAUNCHED();
     j.active = true;

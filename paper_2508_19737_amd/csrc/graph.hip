@@ -8,9 +8,10 @@
 //   unique     keep the first of each run of equal keys, drop sentinels
 //   CSR        rowptr by binary search of each row's first key, colidx from the
 //              low bits, degree = row length
-//   plan       node order by descending degree (ties by id), the CSR relabelled
-//              into that order: the hop kernel then sees degree-homogeneous
-//              waves and the heavy rows first
+//   plan       node order by descending degree (ties by id) and the CSR
+//              relabelled into it: the hop kernel then sees degree-homogeneous
+//              waves, the heavy rows first, and the most gathered rows packed
+//              together
 //   merge      (stream_add) resident keys and increment keys merged by rank,
 //              duplicates dropped, CSR and plan rebuilt
 #include "internal.h"
@@ -149,19 +150,21 @@ __global__ void perm_kernel(const uint64_t *__restrict__ keys, int64_t N, uint64
     ideg[k] = deg[node];
 }
 
-// internal row k = node perm[k]; its neighbours relabelled to internal ids.
-// 16 lanes per row.
-__global__ __launch_bounds__(T256) void relabel_kernel(
-    const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
-    const int64_t *__restrict__ irowptr, int64_t N, int32_t *__restrict__ icolidx) {
-    const int64_t k = (int64_t)blockIdx.x * (T256 / 16) + (threadIdx.x >> 4);
-    const int l = threadIdx.x & 15;
-    if (k >= N) return;
-    const int32_t node = perm[k];
-    const int64_t b = rowptr[node], e = rowptr[node + 1];
-    const int64_t o = irowptr[k];
-    for (int64_t t = b + l; t < e; t += 16) icolidx[o + (t - b)] = iperm[colidx[t]];
+// One thread per stored entry p of the canonical CSR (unique key (i, j)):
+// its place in the relabelled CSR is irowptr[iperm[i]] + (p - rowptr[i]) and
+// its column becomes iperm[j].  Entries are independent, so many lookups are
+// in flight at once.
+__global__ void relabel_kernel(const uint64_t *__restrict__ uk, int64_t nnz, int B,
+                               const int64_t *__restrict__ rowptr,
+                               const int32_t *__restrict__ iperm,
+                               const int64_t *__restrict__ irowptr,
+                               int32_t *__restrict__ icolidx) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const uint64_t key = uk[p];
+    const int64_t i = (int64_t)(key >> B);
+    const int64_t j = (int64_t)(key & (((uint64_t)1 << B) - 1));
+    icolidx[irowptr[iperm[i]] + (p - rowptr[i])] = iperm[j];
 }
 
 // keys of a canonical CSR, packed with B bits per id: (row << B) | col
@@ -305,10 +308,12 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t nnz, int B, int64_t N, hipS
     IFGP_TRY(exclusive_scan<int32_t>(ideg.as<int32_t>(), g.irowptr.as<int64_t>(), N,
                                      g.irowptr.as<int64_t>() + N, s));
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * nnz, s));
-    relabel_kernel<<<grid1(N, 16), T256, 0, s>>>(
-        g.rowptr.as<int64_t>(), g.colidx.as<int32_t>(), g.perm.as<int32_t>(),
-        g.iperm.as<int32_t>(), g.irowptr.as<int64_t>(), N, g.icolidx.as<int32_t>());
-    IFGP_LAUNCHED();
+    if (nnz > 0) {
+        relabel_kernel<<<grid1(nnz), T256, 0, s>>>(uk, nnz, B, g.rowptr.as<int64_t>(),
+                                                   g.iperm.as<int32_t>(), g.irowptr.as<int64_t>(),
+                                                   g.icolidx.as<int32_t>());
+        IFGP_LAUNCHED();
+    }
     return IFGP_OK;
 }
 

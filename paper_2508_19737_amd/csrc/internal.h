@@ -32,7 +32,8 @@ struct GraphData {
     Buf rowptr;   // int64 N+1
     Buf colidx;   // int32 nnz
     Buf deg;      // int32 N
-    // plan: internal row k holds node perm[k]; rows sorted by degree, descending
+    // plan: internal row k holds node perm[k]; rows sorted by degree,
+    // descending (ties by id); the CSR relabelled into that order
     Buf perm;     // int32 N
     Buf iperm;    // int32 N (node -> internal row)
     Buf irowptr;  // int64 N+1
@@ -45,6 +46,7 @@ struct Scales {
     bool valid = false;
     double tau = 0, eps = 0;
     Buf s64;       // double N: (D_tau)^{-1/2}
+    Buf s32;       // float N: s64 rounded, gathered to form r
     Buf nodeinfo;  // float4 N: (s, sqrt(D_tau), sum_{j in N(i)} s_j, 0)
 };
 
@@ -70,6 +72,8 @@ struct Job {
 struct ifgp_graph_s {
     int device = 0;
     hipStream_t stream = nullptr;   // stream of the most recent call
+    hipStream_t aux = nullptr;      // library-owned stream for independent work
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ifgp::GraphData g;
     ifgp::Scales sc;
     ifgp::Workspace ws;
