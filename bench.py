@@ -41,12 +41,6 @@ def hop_bytes_compulsory(N, nnz, Dp, b, blocks):
     return 4 * nnz + 8 * (N + 1) + 16 * N + 2 * b * N * Dp + 16 * Dp * blocks
 
 
-def hop_blocks(N, deg):
-    hub = int((deg >= 4096).sum())
-    med = int((deg >= 256).sum()) - hub
-    return hub + -(-med // 4) + -(-(N - hub - med) // 256)
-
-
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hop_kernel_dcsbm2M_bf16_d64_counters.md")
 KERNEL_SOURCES = ["paper_2508_19737_amd/csrc/ffp.hip", "paper_2508_19737_amd/csrc/internal.h",
                   "paper_2508_19737_amd/csrc/common.h"]
@@ -271,8 +265,7 @@ def main():
     hop_ms_avg = hop_ms / max(n_hops, 1)
     say(f"step {t_step*1e3:.3f} ms, embed {t_embed*1e3:.3f} ms, hop {hop_ms_avg:.4f} ms x {n_hops}")
 
-    _, _, deg = G.export_csr()
-    blocks = hop_blocks(a.N, deg)
+    blocks = G.plan_info()["hop_blocks"]
     Dp = max(8, 1 << (a.d - 1).bit_length())
     b = {"bf16": 2, "f16": 2, "f32": 4}[a.storage]
     bytes_hop = hop_bytes(a.N, nnz, Dp, b, blocks)

@@ -192,6 +192,14 @@ IFGP_API ifgp_status ifgp_job_step(ifgp_graph_t *gs, int32_t n, int32_t *done_fl
 IFGP_API ifgp_status ifgp_graph_info(ifgp_graph_t g, int64_t *N, int64_t *nnz,
                             int64_t *self_loops_dropped, int64_t *dups_dropped);
 
+/* The execution plan of the hop kernel: rows with at least 4096 neighbours
+ * (one 256-thread block each, by default), rows with at least 256 (one wave
+ * each, by default), the
+ * number of thread blocks one hop launches, and the largest degree.  Any
+ * output pointer may be NULL. */
+IFGP_API ifgp_status ifgp_plan_info(ifgp_graph_t g, int64_t *hub_rows, int64_t *medium_rows,
+                                    int64_t *hop_blocks, int32_t *max_degree);
+
 /* Copy the CSR to host memory: rowptr N+1 entries, colidx nnz entries (ascending
  * within each row), deg N entries.  Synchronises the stream of the last call. */
 IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *colidx, int32_t *deg);

@@ -24,7 +24,8 @@ DTYPES = {"f32": F32, "fp32": F32, "float32": F32, "bf16": BF16, "bfloat16": BF1
 EXPORTS = [
     "ifgp_default_params", "ifgp_build_graph", "ifgp_embed", "ifgp_embed_x",
     "ifgp_gaussian_input", "ifgp_stream_add", "ifgp_embed_batch", "ifgp_job_begin",
-    "ifgp_job_step", "ifgp_graph_info", "ifgp_export_csr", "ifgp_export_scales",
+    "ifgp_job_step", "ifgp_graph_info", "ifgp_plan_info", "ifgp_export_csr",
+    "ifgp_export_scales",
     "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_empty_cache", "ifgp_timing_enable",
     "ifgp_timing_read",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
@@ -64,6 +65,7 @@ def _load():
         "ifgp_job_begin": [P, f64, i32, i32, u64, PP, P, P],
         "ifgp_job_step": [P, i32, P, P],
         "ifgp_graph_info": [P, P, P, P, P],
+        "ifgp_plan_info": [P, P, P, P, P],
         "ifgp_export_csr": [P, P, P, P],
         "ifgp_export_scales": [P, f64, f64, P],
         "ifgp_footprint_bytes": [i64, i64, i32, i32, P],
@@ -203,6 +205,13 @@ class Graph:
         check(lib.ifgp_graph_info(self.handle, *[ctypes.byref(x) for x in v]))
         N, nnz, loops, dups = (int(x.value) for x in v)
         return {"N": N, "nnz": nnz, "self_loops_dropped": loops, "dups_dropped": dups}
+
+    def plan_info(self):
+        v = [ctypes.c_int64() for _ in range(3)]
+        md = ctypes.c_int32()
+        check(lib.ifgp_plan_info(self.handle, *[ctypes.byref(x) for x in v], ctypes.byref(md)))
+        return {"hub_rows": int(v[0].value), "medium_rows": int(v[1].value),
+                "hop_blocks": int(v[2].value), "max_degree": int(md.value)}
 
     @property
     def N(self):

@@ -391,6 +391,16 @@ IFGP_API ifgp_status ifgp_graph_info(ifgp_graph_t g, int64_t *N, int64_t *nnz, i
     return IFGP_OK;
 }
 
+IFGP_API ifgp_status ifgp_plan_info(ifgp_graph_t g, int64_t *hub_rows, int64_t *medium_rows,
+                                    int64_t *hop_blocks, int32_t *max_degree) {
+    IFGP_TRY(check_handle(g));
+    if (hub_rows) *hub_rows = g->g.n_hub;
+    if (medium_rows) *medium_rows = g->g.n_med;
+    if (hop_blocks) *hop_blocks = ifgp::hop_blocks(g->g, 64, IFGP_BF16);  // BF16, width 64
+    if (max_degree) *max_degree = g->g.max_deg;
+    return IFGP_OK;
+}
+
 IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *colidx, int32_t *deg) {
     IFGP_TRY(check_handle(g));
     IFGP_TRY(use_device(g));
@@ -434,7 +444,7 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
     // two feature buffers, block statistics (bounded by the row classes:
     // hub rows <= nnz / HUB_DEGREE, medium rows <= nnz / MED_DEGREE), coefficients
     const int64_t blocks = nnz / HUB_DEGREE + ceil_div(nnz / MED_DEGREE, MED_ROWS_PER_BLOCK) +
-                           ceil_div(N, LIGHT_ROWS_PER_BLOCK) + 2;
+                           ceil_div(N, light_rows_per_block(1)) + 2;
     total += 2 * N * Dp * (int64_t)b + 16 * Dp * blocks + 8 * Dp;
     *bytes = total;
     return IFGP_OK;

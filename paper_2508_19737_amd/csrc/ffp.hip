@@ -21,7 +21,7 @@
 // vectors by LPR = D / (16 / sizeof(T)) lanes.  Rows are in descending-degree
 // order (plan built with the graph), split into three classes:
 //   hub     deg >= 4096  one 256-thread block per row
-//   medium  deg >= 256   one wave per row (subgroups split the neighbours)
+//   medium  deg >= 128   one wave per row (subgroups split the neighbours)
 //   light   the rest     one LPR-lane subgroup per row, 256 rows per block
 // Heavy rows come first in the grid, so long blocks start early.
 #include <cmath>
@@ -36,15 +36,25 @@ namespace {
 
 constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / 64;
-constexpr int U = 8;   // neighbour rows in flight per lane
+// Neighbour rows in flight per lane: 16-byte loads of 4-byte storage cover
+// half as many columns as those of 2-byte storage, so they get twice the
+// depth.
+#ifndef IFGP_HOP_UNROLL_2B
+#define IFGP_HOP_UNROLL_2B 8
+#endif
+#ifndef IFGP_HOP_UNROLL_4B
+#define IFGP_HOP_UNROLL_4B 16
+#endif
 
 template <typename T, int D> struct Cfg {
+    static constexpr int U = sizeof(T) == 4 ? IFGP_HOP_UNROLL_4B : IFGP_HOP_UNROLL_2B;
     static constexpr int EPL = 16 / (int)sizeof(T);   // elements per lane
     static constexpr int LPR = D / EPL;               // lanes per row
     static constexpr int RPW = 64 / LPR;              // rows (subgroups) per wave
     static constexpr int QI = (U + LPR - 1) / LPR;    // index loads per lane per chunk
+    static constexpr int LIGHT_ROWS = light_rows_per_block(RPW);
     static_assert(LPR >= 1 && LPR <= 64 && (64 % LPR) == 0, "unsupported width");
-    static_assert(LIGHT_ROWS_PER_BLOCK % (WAVES * RPW) == 0, "light block shape");
+    static_assert(LIGHT_ROWS % (WAVES * RPW) == 0, "light block shape");
 };
 
 // ---------------------------------------------------------------- pack/unpack
@@ -285,7 +295,7 @@ __device__ __forceinline__ void gather_add(const int32_t *__restrict__ colidx,
                                            int64_t end, int64_t step, int sl, int lane_base,
                                            float *acc) {
     using C = Cfg<T, D>;
-    constexpr int EPL = C::EPL, LPR = C::LPR, QI = C::QI;
+    constexpr int EPL = C::EPL, LPR = C::LPR, QI = C::QI, U = C::U;
     const int64_t col_off = (int64_t)sl * EPL * (int64_t)sizeof(T);
     for (int64_t e0 = first; e0 < end; e0 += step) {
         int32_t idx[QI];
@@ -347,7 +357,7 @@ __device__ __forceinline__ void row_finish(const HopArgs &a, int64_t r, int sl, 
 template <typename T, int D>
 __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
     using C = Cfg<T, D>;
-    constexpr int EPL = C::EPL, LPR = C::LPR, RPW = C::RPW;
+    constexpr int EPL = C::EPL, LPR = C::LPR, RPW = C::RPW, U = C::U;
     __shared__ float lds_acc[WAVES][D];
     __shared__ double2 lds_st[WAVES][D];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -407,9 +417,8 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
         }
     } else {
         // light: one LPR-lane subgroup per row
-        const int64_t row0 =
-            a.n_hub + a.n_med + (blk - a.blk_med_end) * (int64_t)LIGHT_ROWS_PER_BLOCK;
-        constexpr int PASSES = LIGHT_ROWS_PER_BLOCK / (WAVES * RPW);
+        const int64_t row0 = a.n_hub + a.n_med + (blk - a.blk_med_end) * (int64_t)C::LIGHT_ROWS;
+        constexpr int PASSES = C::LIGHT_ROWS / (WAVES * RPW);
         for (int p = 0; p < PASSES; ++p) {
             const int64_t r = row0 + (int64_t)p * WAVES * RPW + w * RPW + g;
             if (r < a.N) {
@@ -595,11 +604,7 @@ __global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
 }
 
 // ---------------------------------------------------------------- host side
-template <typename T, int D> int64_t blocks_for(const GraphData &g) {
-    const int64_t n_light = g.N - g.n_hub - g.n_med;
-    return g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK) +
-           ceil_div(n_light, LIGHT_ROWS_PER_BLOCK);
-}
+
 
 #define IFGP_WIDTHS(T, Dp, CALL)                                  \
     switch (Dp) {                                                 \
@@ -740,11 +745,10 @@ ifgp_status record_event(ifgp_graph_s *h, hipStream_t s, bool start) {
 }  // namespace
 
 int64_t hop_blocks(const GraphData &g, int Dp, int storage) {
-    (void)Dp;
-    (void)storage;
-    // block count does not depend on the width: every class has a fixed
-    // number of rows per block
-    return blocks_for<float, 64>(g);
+    const int64_t n_light = g.N - g.n_hub - g.n_med;
+    const int rpw = 1024 / ((int)dtype_bytes(storage) * Dp);   // 64 / lanes per row
+    return g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK) +
+           ceil_div(n_light, light_rows_per_block(rpw));
 }
 
 ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,

@@ -18,10 +18,24 @@ ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int bits, hipStr
 
 // Row classes of the hop kernel, by degree.  Rows are kept in descending-
 // degree order, so each class is a contiguous range of internal rows.
-constexpr int64_t HUB_DEGREE = 4096;  // >= : one 256-thread block per row
-constexpr int64_t MED_DEGREE = 256;   // >= : one wave per row
+// The defaults can be overridden at compile time (-DIFGP_HUB_DEGREE=...).
+#ifndef IFGP_HUB_DEGREE
+#define IFGP_HUB_DEGREE 4096
+#endif
+#ifndef IFGP_MED_DEGREE
+#define IFGP_MED_DEGREE 128
+#endif
+#ifndef IFGP_LIGHT_ROWS
+#define IFGP_LIGHT_ROWS 256
+#endif
+constexpr int64_t HUB_DEGREE = IFGP_HUB_DEGREE;  // >= : one 256-thread block per row
+constexpr int64_t MED_DEGREE = IFGP_MED_DEGREE;  // >= : one wave per row
 constexpr int MED_ROWS_PER_BLOCK = 4;
-constexpr int LIGHT_ROWS_PER_BLOCK = 256;
+// Light rows per block: IFGP_LIGHT_ROWS, or one pass of the block (4 waves
+// of rpw rows each) if that is larger.
+constexpr int light_rows_per_block(int rpw) {
+    return IFGP_LIGHT_ROWS > 4 * rpw ? IFGP_LIGHT_ROWS : 4 * rpw;
+}
 
 // Canonical graph plus the execution plan of the hop kernel.
 struct GraphData {
