@@ -14,6 +14,8 @@
 //              together
 //   merge      (stream_add) resident keys and increment keys merged by rank,
 //              duplicates dropped, CSR and plan rebuilt
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ifgp {
@@ -66,30 +68,79 @@ __global__ __launch_bounds__(T256) void ingest_kernel(const int64_t *__restrict_
     }
 }
 
-// flag[i] = 1 for the first key of each run of equal keys whose row is < N
-__global__ void unique_flags_kernel(const uint64_t *__restrict__ k, int64_t n, int B, int64_t N,
-                                    uint8_t *__restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Deduplication of sorted keys in tiles of UQ_ITEMS consecutive keys per
+// thread: key i is kept iff it differs from key i-1 and its row is < N (self
+// loops and padding carry row N).
+constexpr int UQ_ITEMS = 8;
+constexpr int UQ_TILE = T256 * UQ_ITEMS;
+
+__device__ __forceinline__ bool keep_key(const uint64_t *__restrict__ k, int64_t i, int B,
+                                         int64_t N) {
     const uint64_t x = k[i];
-    const bool first = (i == 0) || (k[i - 1] != x);
-    flag[i] = (first && (int64_t)(x >> B) < N) ? 1 : 0;
+    return (i == 0 || k[i - 1] != x) && (int64_t)(x >> B) < N;
 }
 
-__global__ void compact_kernel(const uint64_t *__restrict__ k, const uint8_t *__restrict__ flag,
-                               const int64_t *__restrict__ pos, int64_t n,
-                               uint64_t *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flag[i]) out[pos[i]] = k[i];
+__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t &total) {
+    __shared__ int64_t wsum[T256 / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < T256 / 64; ++i) {
+        if (i < w) before += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(T256) void unique_count_kernel(const uint64_t *__restrict__ k,
+                                                            int64_t n, int B, int64_t N,
+                                                            int64_t *__restrict__ bcount) {
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + (int64_t)threadIdx.x * UQ_ITEMS;
+    int64_t c = 0;
+#pragma unroll
+    for (int q = 0; q < UQ_ITEMS; ++q)
+        if (base + q < n && keep_key(k, base + q, B, N)) ++c;
+    int64_t tot;
+    block_excl_scan_i64(c, tot);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__restrict__ k,
+                                                            int64_t n, int B, int64_t N,
+                                                            const int64_t *__restrict__ boff,
+                                                            uint64_t *__restrict__ out) {
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + (int64_t)threadIdx.x * UQ_ITEMS;
+    bool keep[UQ_ITEMS];
+    int64_t c = 0;
+#pragma unroll
+    for (int q = 0; q < UQ_ITEMS; ++q) {
+        keep[q] = base + q < n && keep_key(k, base + q, B, N);
+        c += keep[q];
+    }
+    int64_t tot;
+    int64_t pos = boff[blockIdx.x] + block_excl_scan_i64(c, tot);
+#pragma unroll
+    for (int q = 0; q < UQ_ITEMS; ++q)
+        if (keep[q]) out[pos++] = k[base + q];
 }
 
 // rowptr[r] = first index p with ukeys[p] >= (r << B), r = 0..N
-__global__ void rowptr_kernel(const uint64_t *__restrict__ uk, int64_t nnz, int B, int64_t N,
-                              int64_t *__restrict__ rowptr) {
+__global__ void rowptr_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
+                              int B, int64_t N, int64_t *__restrict__ rowptr) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > N) return;
     const uint64_t target = (uint64_t)r << B;
-    int64_t lo = 0, hi = nnz;
+    int64_t lo = 0, hi = *nnz_d;
     while (lo < hi) {
         const int64_t mid = lo + ((hi - lo) >> 1);
         if (uk[mid] < target) lo = mid + 1;
@@ -98,33 +149,41 @@ __global__ void rowptr_kernel(const uint64_t *__restrict__ uk, int64_t nnz, int 
     rowptr[r] = lo;
 }
 
-__global__ void colidx_kernel(const uint64_t *__restrict__ uk, int64_t nnz, uint64_t mask,
-                              int32_t *__restrict__ colidx) {
+__global__ void colidx_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
+                              int64_t bound, uint64_t mask, int32_t *__restrict__ colidx) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nnz) colidx[p] = (int32_t)(uk[p] & mask);
+    if (p < bound && p < *nnz_d) colidx[p] = (int32_t)(uk[p] & mask);
 }
 
 // deg and the statistics the plan needs: stats[0] = max degree,
-// stats[1] = rows with deg >= HUB_DEGREE, stats[2] = rows with deg >= MED_DEGREE
+// stats[1] = rows with deg >= HUB_DEGREE, stats[2] = rows with deg >= MED_DEGREE.
+// Grid-stride over rows, so that few blocks meet at the atomics.
 __global__ __launch_bounds__(T256) void degree_kernel(const int64_t *__restrict__ rowptr,
                                                       int64_t N, int32_t *__restrict__ deg,
                                                       int64_t *__restrict__ stats) {
-    const int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x;
-    int64_t dg = 0;
-    if (i < N) {
-        dg = rowptr[i + 1] - rowptr[i];
+    int64_t mx = 0, hub = 0, med = 0;
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * T256) {
+        const int64_t dg = rowptr[i + 1] - rowptr[i];
         deg[i] = (int32_t)dg;
+        mx = dg > mx ? dg : mx;
+        hub += dg >= HUB_DEGREE;
+        med += dg >= MED_DEGREE;
     }
-    int64_t mx = dg;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
     __shared__ int64_t red[T256 / 64];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
-    mx = max(max(red[0], red[1]), max(red[2], red[3]));
+    mx = red[0];
+#pragma unroll
+    for (int i = 1; i < T256 / 64; ++i) mx = red[i] > mx ? red[i] : mx;
     __syncthreads();
-    const int64_t hub = block_sum_i64(dg >= HUB_DEGREE ? 1 : 0);
-    const int64_t med = block_sum_i64(dg >= MED_DEGREE ? 1 : 0);
+    hub = block_sum_i64(hub);
+    med = block_sum_i64(med);
     if (threadIdx.x == 0) {
         atomicMax((unsigned long long *)&stats[0], (unsigned long long)mx);
         if (hub) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)hub);
@@ -180,10 +239,14 @@ __global__ __launch_bounds__(T256) void csr_keys_kernel(const int64_t *__restric
 }
 
 // Stable merge by rank: a[i] goes to i + #{b < a[i]}, b[j] to j + #{a <= b[j]}.
+// b holds *nb_d valid keys out of nb_bound; output slots past na + *nb_d get
+// the sentinel, so the whole output stays sorted.
 __global__ void merge_rank_kernel(const uint64_t *__restrict__ a, int64_t na,
-                                  const uint64_t *__restrict__ b, int64_t nb,
+                                  const uint64_t *__restrict__ b, const int64_t *__restrict__ nb_d,
+                                  int64_t nb_bound, uint64_t sentinel,
                                   uint64_t *__restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = *nb_d;
     if (t < na) {
         const uint64_t x = a[t];
         int64_t lo = 0, hi = nb;
@@ -193,16 +256,20 @@ __global__ void merge_rank_kernel(const uint64_t *__restrict__ a, int64_t na,
             else hi = mid;
         }
         out[t + lo] = x;
-    } else if (t < na + nb) {
+    } else if (t < na + nb_bound) {
         const int64_t j = t - na;
-        const uint64_t x = b[j];
-        int64_t lo = 0, hi = na;
-        while (lo < hi) {
-            const int64_t mid = lo + ((hi - lo) >> 1);
-            if (a[mid] <= x) lo = mid + 1;
-            else hi = mid;
+        if (j < nb) {
+            const uint64_t x = b[j];
+            int64_t lo = 0, hi = na;
+            while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (a[mid] <= x) lo = mid + 1;
+                else hi = mid;
+            }
+            out[j + lo] = x;
+        } else {
+            out[t] = sentinel;
         }
-        out[j + lo] = x;
     }
 }
 
@@ -214,77 +281,74 @@ ifgp_status copy_d2h_sync(void *h, const void *d, size_t bytes, hipStream_t s) {
     return IFGP_OK;
 }
 
-// Keys of E pairs -> 2E keys; reports self-loop pairs, fails on bad ids.
+// Device counters of one build, read back by the single host synchronisation.
+enum { C_LOOPS = 0, C_BAD, C_NNZ, C_MAXDEG, C_HUB, C_MED, C_COUNT };
+
+// Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the device.
 ifgp_status ingest(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
-                   hipStream_t s, Buf &keys, int64_t &loops) {
+                   hipStream_t s, Buf &keys, int64_t *ctr) {
     IFGP_TRY(alloc(keys, sizeof(uint64_t) * 2 * E, s));
-    Buf cnt;
-    IFGP_TRY(alloc(cnt, sizeof(int64_t) * 2, s));
-    IFGP_TRY(fill_i64(cnt.as<int64_t>(), 2, 0, s));
     if (E > 0) {
         ingest_kernel<<<grid1(E), T256, 0, s>>>(src, dst, E, N, B, keys.as<uint64_t>(),
-                                                cnt.as<int64_t>());
+                                                ctr + C_LOOPS);
         IFGP_LAUNCHED();
     }
-    int64_t h[2] = {0, 0};
-    IFGP_TRY(copy_d2h_sync(h, cnt.p, sizeof(h), s));
-    if (h[1]) {
+    return IFGP_OK;
+}
+
+// n sorted keys (repeats and sentinels allowed) -> unique keys; the count goes
+// to *nu_d on the device; uk is allocated for the upper bound n.
+ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStream_t s, Buf &uk,
+                        int64_t *nu_d) {
+    IFGP_TRY(alloc(uk, sizeof(uint64_t) * n, s));
+    const int64_t nb = ceil_div(n, UQ_TILE);
+    Buf bc;
+    IFGP_TRY(alloc(bc, sizeof(int64_t) * (nb + 1), s));
+    if (n > 0) {
+        unique_count_kernel<<<(unsigned)nb, T256, 0, s>>>(k, n, B, N, bc.as<int64_t>());
+        IFGP_LAUNCHED();
+    }
+    IFGP_TRY(exclusive_scan<int64_t>(bc.as<int64_t>(), bc.as<int64_t>(), nb, nu_d, s));
+    if (n > 0) {
+        unique_write_kernel<<<(unsigned)nb, T256, 0, s>>>(k, n, B, N, bc.as<int64_t>(),
+                                                          uk.as<uint64_t>());
+        IFGP_LAUNCHED();
+    }
+    return IFGP_OK;
+}
+
+// Unique sorted keys (count on the device, at most bound) -> canonical CSR
+// and plan.  The one host synchronisation of a build happens here.
+ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hipStream_t s,
+                         int64_t *ctr, GraphData &g) {
+    g.N = N;
+    IFGP_TRY(alloc(g.rowptr, sizeof(int64_t) * (N + 1), s));
+    IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * bound, s));
+    IFGP_TRY(alloc(g.deg, sizeof(int32_t) * N, s));
+    rowptr_kernel<<<grid1(N + 1), T256, 0, s>>>(uk, ctr + C_NNZ, B, N, g.rowptr.as<int64_t>());
+    IFGP_LAUNCHED();
+    if (bound > 0) {
+        colidx_kernel<<<grid1(bound), T256, 0, s>>>(uk, ctr + C_NNZ, bound,
+                                                    ((uint64_t)1 << B) - 1,
+                                                    g.colidx.as<int32_t>());
+        IFGP_LAUNCHED();
+    }
+    const unsigned dgrid = (unsigned)std::min<int64_t>(grid1(N), 1024);
+    degree_kernel<<<dgrid, T256, 0, s>>>(g.rowptr.as<int64_t>(), N, g.deg.as<int32_t>(),
+                                         ctr + C_MAXDEG);
+    IFGP_LAUNCHED();
+    int64_t h[C_COUNT];
+    IFGP_TRY(copy_d2h_sync(h, ctr, sizeof(h), s));
+    if (h[C_BAD]) {
         set_error("edge list holds a node id outside [0, %lld)", (long long)N);
         return IFGP_E_RANGE;
     }
-    loops = h[0];
-    return IFGP_OK;
-}
-
-// Sorted keys (n of them, some may repeat or be sentinels) -> unique keys.
-ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStream_t s, Buf &uk,
-                        int64_t &nu) {
-    Buf flag, pos, tot;
-    IFGP_TRY(alloc(flag, n, s));
-    IFGP_TRY(alloc(pos, sizeof(int64_t) * n, s));
-    IFGP_TRY(alloc(tot, sizeof(int64_t), s));
-    if (n > 0) {
-        unique_flags_kernel<<<grid1(n), T256, 0, s>>>(k, n, B, N, flag.as<uint8_t>());
-        IFGP_LAUNCHED();
-    }
-    IFGP_TRY(exclusive_scan<uint8_t>(flag.as<uint8_t>(), pos.as<int64_t>(), n, tot.as<int64_t>(),
-                                     s));
-    IFGP_TRY(copy_d2h_sync(&nu, tot.p, sizeof(int64_t), s));
-    IFGP_TRY(alloc(uk, sizeof(uint64_t) * nu, s));
-    if (n > 0) {
-        compact_kernel<<<grid1(n), T256, 0, s>>>(k, flag.as<uint8_t>(), pos.as<int64_t>(), n,
-                                                 uk.as<uint64_t>());
-        IFGP_LAUNCHED();
-    }
-    return IFGP_OK;
-}
-
-// Unique sorted keys -> canonical CSR + plan.
-ifgp_status csr_and_plan(const uint64_t *uk, int64_t nnz, int B, int64_t N, hipStream_t s,
-                         GraphData &g) {
-    g.N = N;
+    const int64_t nnz = h[C_NNZ];
     g.nnz = nnz;
-    IFGP_TRY(alloc(g.rowptr, sizeof(int64_t) * (N + 1), s));
-    IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * nnz, s));
-    IFGP_TRY(alloc(g.deg, sizeof(int32_t) * N, s));
-    rowptr_kernel<<<grid1(N + 1), T256, 0, s>>>(uk, nnz, B, N, g.rowptr.as<int64_t>());
-    IFGP_LAUNCHED();
-    if (nnz > 0) {
-        colidx_kernel<<<grid1(nnz), T256, 0, s>>>(uk, nnz, ((uint64_t)1 << B) - 1,
-                                                  g.colidx.as<int32_t>());
-        IFGP_LAUNCHED();
-    }
-    Buf stats;
-    IFGP_TRY(alloc(stats, sizeof(int64_t) * 3, s));
-    IFGP_TRY(fill_i64(stats.as<int64_t>(), 3, 0, s));
-    degree_kernel<<<grid1(N), T256, 0, s>>>(g.rowptr.as<int64_t>(), N, g.deg.as<int32_t>(),
-                                            stats.as<int64_t>());
-    IFGP_LAUNCHED();
-    int64_t st[3];
-    IFGP_TRY(copy_d2h_sync(st, stats.p, sizeof(st), s));
-    g.max_deg = (int32_t)st[0];
-    g.n_hub = st[1];
-    g.n_med = st[2] - st[1];
+    g.self_loops = h[C_LOOPS];
+    g.max_deg = (int32_t)h[C_MAXDEG];
+    g.n_hub = h[C_HUB];
+    g.n_med = h[C_MED] - h[C_HUB];
 
     // node order by descending degree
     const int dbits = bit_width((uint64_t)g.max_deg);
@@ -322,22 +386,22 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t nnz, int B, int64_t N, hipS
 ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
                                hipStream_t s, GraphData &out) {
     const int B = bit_width((uint64_t)N);  // holds 0..N (N is the sentinel row)
+    Buf ctr;
+    IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
+    IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
     Buf keys;
-    int64_t loops = 0;
-    IFGP_TRY(ingest(src, dst, E, N, B, s, keys, loops));
+    IFGP_TRY(ingest(src, dst, E, N, B, s, keys, ctr.as<int64_t>()));
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(uint64_t) * 2 * E, s));
     uint64_t *sorted = nullptr;
     IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 2 * B, s, &sorted));
     Buf uk;
-    int64_t nnz = 0;
-    IFGP_TRY(unique_keys(sorted, 2 * E, B, N, s, uk, nnz));
+    IFGP_TRY(unique_keys(sorted, 2 * E, B, N, s, uk, ctr.as<int64_t>() + C_NNZ));
     keys.reset();
     tmp.reset();
     GraphData g;
-    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), nnz, B, N, s, g));
-    g.self_loops = loops;
-    g.dups = (E - loops) - nnz / 2;
+    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), 2 * E, B, N, s, ctr.as<int64_t>(), g));
+    g.dups = (E - g.self_loops) - g.nnz / 2;
     out = std::move(g);
     return IFGP_OK;
 }
@@ -345,17 +409,19 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
 ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const int64_t *dst,
                                int64_t E, int64_t new_N, hipStream_t s, GraphData &out) {
     const int B = bit_width((uint64_t)new_N);
-    // increment: keys, sort, unique
+    Buf ctr, cinc;
+    IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
+    IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
+    IFGP_TRY(alloc(cinc, sizeof(int64_t), s));
+    // increment: keys, sort, unique (count of unique increment keys in cinc)
     Buf keys;
-    int64_t loops = 0;
-    IFGP_TRY(ingest(src, dst, E, new_N, B, s, keys, loops));
+    IFGP_TRY(ingest(src, dst, E, new_N, B, s, keys, ctr.as<int64_t>()));
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(uint64_t) * 2 * E, s));
     uint64_t *sorted = nullptr;
     IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 2 * B, s, &sorted));
     Buf inc;
-    int64_t ninc = 0;
-    IFGP_TRY(unique_keys(sorted, 2 * E, B, new_N, s, inc, ninc));
+    IFGP_TRY(unique_keys(sorted, 2 * E, B, new_N, s, inc, cinc.as<int64_t>()));
     keys.reset();
     tmp.reset();
     // resident keys repacked with B bits (row-major order is unchanged)
@@ -368,25 +434,25 @@ ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const in
         IFGP_LAUNCHED();
     }
     Buf merged;
-    const int64_t nm = in.nnz + ninc;
+    const int64_t nm = in.nnz + 2 * E;   // upper bound; unused slots hold the sentinel
     IFGP_TRY(alloc(merged, sizeof(uint64_t) * nm, s));
     if (nm > 0) {
         merge_rank_kernel<<<grid1(nm), T256, 0, s>>>(res.as<uint64_t>(), in.nnz,
-                                                     inc.as<uint64_t>(), ninc,
+                                                     inc.as<uint64_t>(), cinc.as<int64_t>(),
+                                                     2 * E, (uint64_t)new_N << B,
                                                      merged.as<uint64_t>());
         IFGP_LAUNCHED();
     }
     res.reset();
     inc.reset();
     Buf uk;
-    int64_t nnz = 0;
-    IFGP_TRY(unique_keys(merged.as<uint64_t>(), nm, B, new_N, s, uk, nnz));
+    IFGP_TRY(unique_keys(merged.as<uint64_t>(), nm, B, new_N, s, uk, ctr.as<int64_t>() + C_NNZ));
     merged.reset();
     GraphData g;
-    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), nnz, B, new_N, s, g));
-    g.self_loops = in.self_loops + loops;
+    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), nm, B, new_N, s, ctr.as<int64_t>(), g));
+    g.self_loops += in.self_loops;
     // pairs of this increment that added no new edge
-    g.dups = in.dups + (E - loops) - (nnz - in.nnz) / 2;
+    g.dups = in.dups + (E - (g.self_loops - in.self_loops)) - (g.nnz - in.nnz) / 2;
     out = std::move(g);
     return IFGP_OK;
 }

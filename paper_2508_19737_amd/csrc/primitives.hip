@@ -164,11 +164,16 @@ __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_TILE;
     const uint64_t lt = __lanemask_lt();
+    uint64_t key[RS_ROUNDS];
+#pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int64_t idx = t0 + r * 64 + lane;
-        const bool valid = idx < n;
-        const uint64_t k = valid ? keys[idx] : 0;
-        const unsigned g = (unsigned)(k >> shift) & (RS_BINS - 1);
+        key[r] = idx < n ? keys[idx] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const bool valid = t0 + r * 64 + lane < n;
+        const unsigned g = (unsigned)(key[r] >> shift) & (RS_BINS - 1);
         const uint64_t m = match_digit(g, valid);
         // one leader per distinct digit updates the wave's counter
         if (valid && __popcll(m & lt) == 0) cnt[w][g] += __popcll(m);
@@ -180,26 +185,35 @@ __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *
     hist[(int64_t)tid * nb + blockIdx.x] = tot;
 }
 
-// Stable scatter: key order within the block is (wave, round, lane).
+// Stable scatter.  Key order within the block is (wave, round, lane).  The
+// tile is first placed in LDS in digit order, then each digit's run is
+// written to its global range by consecutive threads (coalesced stores).
 __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
     const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n, int shift,
     const int64_t *__restrict__ offs, int64_t nb) {
     __shared__ int cnt[RS_WAVES][RS_BINS];
-    __shared__ int64_t base[RS_BINS];
+    __shared__ int tstart[RS_BINS];
+    __shared__ int wsum[RS_WAVES];
+    __shared__ int64_t gbase[RS_BINS];
+    __shared__ uint64_t lkeys[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int i = tid; i < RS_WAVES * RS_BINS; i += RS_THREADS) (&cnt[0][0])[i] = 0;
-    base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    gbase[tid] = offs[(int64_t)tid * nb + blockIdx.x];
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_TILE;
+    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t t0 = tile0 + (int64_t)w * RS_WAVE_TILE;
     const uint64_t lt = __lanemask_lt();
     uint64_t key[RS_ROUNDS];
     int rank[RS_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int64_t idx = t0 + r * 64 + lane;
-        const bool valid = idx < n;
-        const uint64_t k = valid ? in[idx] : 0;
-        const unsigned g = (unsigned)(k >> shift) & (RS_BINS - 1);
+        key[r] = idx < n ? in[idx] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const bool valid = t0 + r * 64 + lane < n;
+        const unsigned g = (unsigned)(key[r] >> shift) & (RS_BINS - 1);
         const uint64_t m = match_digit(g, valid);
         const int below = __popcll(m & lt);
         int c = 0;
@@ -207,26 +221,45 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
         // The leader's write depends on the value all lanes just read, so the
         // read of this wave completes before the write is issued.
         if (valid && below == 0) cnt[w][g] = c + __popcll(m);
-        key[r] = k;
         rank[r] = valid ? c + below : -1;
     }
     __syncthreads();
-    {
-        int run = 0;
+    // per digit (one per thread): offsets of the waves, and the tile total
+    int total = 0;
 #pragma unroll
-        for (int ww = 0; ww < RS_WAVES; ++ww) {
-            const int t = cnt[ww][tid];
-            cnt[ww][tid] = run;
-            run += t;
-        }
+    for (int ww = 0; ww < RS_WAVES; ++ww) {
+        const int t = cnt[ww][tid];
+        cnt[ww][tid] = total;
+        total += t;
     }
+    // exclusive scan of the 256 digit totals -> tile-local start of each digit
+    int inc = total;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int woff = 0;
+#pragma unroll
+    for (int ww = 0; ww < RS_WAVES; ++ww)
+        if (ww < w) woff += wsum[ww];
+    tstart[tid] = woff + inc - total;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         if (rank[r] >= 0) {
             const unsigned g = (unsigned)(key[r] >> shift) & (RS_BINS - 1);
-            out[base[g] + cnt[w][g] + rank[r]] = key[r];
+            lkeys[tstart[g] + cnt[w][g] + rank[r]] = key[r];
         }
+    }
+    __syncthreads();
+    const int tile_n = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
+    for (int i = tid; i < tile_n; i += RS_THREADS) {
+        const uint64_t k = lkeys[i];
+        const unsigned g = (unsigned)(k >> shift) & (RS_BINS - 1);
+        out[gbase[g] + (i - tstart[g])] = k;
     }
 }
 }  // namespace
