@@ -80,58 +80,56 @@ __device__ __forceinline__ bool keep_key(const uint64_t *__restrict__ k, int64_t
     return (i == 0 || k[i - 1] != x) && (int64_t)(x >> B) < N;
 }
 
-__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t &total) {
-    __shared__ int64_t wsum[T256 / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    int64_t before = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < T256 / 64; ++i) {
-        if (i < w) before += wsum[i];
-        tot += wsum[i];
-    }
-    __syncthreads();
-    total = tot;
-    return before + inc - v;
-}
-
+// Tile t holds keys [t*UQ_TILE, (t+1)*UQ_TILE); round q of the tile gives
+// thread j key t*UQ_TILE + q*T256 + j, so loads and stores are coalesced.
 __global__ __launch_bounds__(T256) void unique_count_kernel(const uint64_t *__restrict__ k,
                                                             int64_t n, int B, int64_t N,
                                                             int64_t *__restrict__ bcount) {
-    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + (int64_t)threadIdx.x * UQ_ITEMS;
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + threadIdx.x;
     int64_t c = 0;
 #pragma unroll
-    for (int q = 0; q < UQ_ITEMS; ++q)
-        if (base + q < n && keep_key(k, base + q, B, N)) ++c;
-    int64_t tot;
-    block_excl_scan_i64(c, tot);
-    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+    for (int q = 0; q < UQ_ITEMS; ++q) {
+        const int64_t i = base + (int64_t)q * T256;
+        if (i < n && keep_key(k, i, B, N)) ++c;
+    }
+    c = block_sum_i64(c);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
 __global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__restrict__ k,
                                                             int64_t n, int B, int64_t N,
                                                             const int64_t *__restrict__ boff,
                                                             uint64_t *__restrict__ out) {
-    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + (int64_t)threadIdx.x * UQ_ITEMS;
+    __shared__ int wcount[UQ_ITEMS][T256 / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + threadIdx.x;
+    const uint64_t lt = __lanemask_lt();
     bool keep[UQ_ITEMS];
-    int64_t c = 0;
+    uint64_t key[UQ_ITEMS];
+    int below[UQ_ITEMS];
 #pragma unroll
     for (int q = 0; q < UQ_ITEMS; ++q) {
-        keep[q] = base + q < n && keep_key(k, base + q, B, N);
-        c += keep[q];
+        const int64_t i = base + (int64_t)q * T256;
+        keep[q] = i < n && keep_key(k, i, B, N);
+        key[q] = keep[q] ? k[i] : 0;
+        const uint64_t m = __ballot(keep[q]);
+        below[q] = __popcll(m & lt);
+        if (lane == 0) wcount[q][w] = __popcll(m);
     }
-    int64_t tot;
-    int64_t pos = boff[blockIdx.x] + block_excl_scan_i64(c, tot);
+    __syncthreads();
+    // kept keys before (round q, wave w): all earlier rounds, then earlier waves
+    int64_t pos = boff[blockIdx.x];
 #pragma unroll
-    for (int q = 0; q < UQ_ITEMS; ++q)
-        if (keep[q]) out[pos++] = k[base + q];
+    for (int q = 0; q < UQ_ITEMS; ++q) {
+        int before = 0, round = 0;
+#pragma unroll
+        for (int ww = 0; ww < T256 / 64; ++ww) {
+            before += ww < w ? wcount[q][ww] : 0;
+            round += wcount[q][ww];
+        }
+        if (keep[q]) out[pos + before + below[q]] = key[q];
+        pos += round;
+    }
 }
 
 // rowptr[r] = first index p with ukeys[p] >= (r << B), r = 0..N

@@ -163,20 +163,19 @@ __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *
     for (int i = tid; i < RS_WAVES * RS_BINS; i += RS_THREADS) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_TILE;
-    const uint64_t lt = __lanemask_lt();
     uint64_t key[RS_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int64_t idx = t0 + r * 64 + lane;
         key[r] = idx < n ? keys[idx] : 0;
     }
+    // Counting needs no ranks: LDS atomics into the wave's own counters (lanes
+    // hitting one digit serialise inside the instruction, which is cheap even
+    // for the few-valued top digit).
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
-        const bool valid = t0 + r * 64 + lane < n;
-        const unsigned g = (unsigned)(key[r] >> shift) & (RS_BINS - 1);
-        const uint64_t m = match_digit(g, valid);
-        // one leader per distinct digit updates the wave's counter
-        if (valid && __popcll(m & lt) == 0) cnt[w][g] += __popcll(m);
+        if (t0 + r * 64 + lane < n)
+            atomicAdd(&cnt[w][(unsigned)(key[r] >> shift) & (RS_BINS - 1)], 1);
     }
     __syncthreads();
     int64_t tot = 0;
