@@ -160,6 +160,27 @@ __device__ __forceinline__ void gaussian4(uint64_t seed, int64_t i, int64_t q, i
     }
 }
 
+// The same four entries with the Box-Muller step in FP32 (the uniforms keep
+// their 53-bit construction and are rounded to FP32 once).  Used only when
+// the result is stored in a 2-byte type, whose rounding (2^-8 or 2^-11) is far
+// coarser than FP32 arithmetic's.
+__device__ __forceinline__ void gaussian4_f32(uint64_t seed, int64_t i, int64_t q, int d, float *z) {
+    uint64_t c0 = (uint64_t)i + 1, c1 = (uint64_t)q, c2 = 0, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, 0);
+    const uint64_t w[4] = {c0, c1, c2, c3};
+    const float inv = 1.0f / sqrtf((float)d);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float ua = (float)(((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53);
+        const float ub = (float)(((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53);
+        const float r = sqrtf(-2.0f * logf(ua));
+        float sn, cs;
+        sincosf(6.2831853071795864769f * ub, &sn, &cs);
+        z[2 * p] = r * cs * inv;
+        z[2 * p + 1] = r * sn * inv;
+    }
+}
+
 // ---------------------------------------------------------------- small kernels
 template <typename T>
 __global__ void gaussian_kernel(int64_t N, int d, uint64_t seed, T *out) {
@@ -189,13 +210,24 @@ __global__ void noise_kernel(int64_t N, int d, uint64_t seed, const int32_t *__r
     if (t >= N * NQ) return;
     const int64_t k = t / NQ;
     const int q = (int)(t % NQ);
-    double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (4 * q < d) gaussian4(seed, perm[k], q, d, z);
     const double sk = s64[k];
+    if constexpr (sizeof(T) == 2) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        if (4 * q < d) gaussian4_f32(seed, perm[k], q, d, z);
+        const float skf = (float)sk;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int c = 4 * q + j;
-        W[k * D + c] = cvt_from_f64<T>(c < d ? sk * z[j] : 0.0);
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * q + j;
+            W[k * D + c] = from_f32<T>(c < d ? skf * z[j] : 0.f);
+        }
+    } else {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (4 * q < d) gaussian4(seed, perm[k], q, d, z);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * q + j;
+            W[k * D + c] = cvt_from_f64<T>(c < d ? sk * z[j] : 0.0);
+        }
     }
 }
 
@@ -238,31 +270,59 @@ __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, do
     s32[k] = (float)sk;
 }
 
-// 16 lanes per row: r_k = sum of s over the row's neighbours (FP32 copies of
-// s gathered, summed in FP64), lanes take strided entries and combine by a
-// fixed butterfly (deterministic order).
-constexpr int NI_LANES = 16;
-__global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N,
+// r_k = sum of s over row k's neighbours (FP32 copies of s gathered, summed in
+// FP64).  Rows are in descending-degree order: the first n_heavy rows get one
+// wave each, the rest NI_LANES lanes each; every lane keeps NI_DEPTH
+// independent gathers in flight and the lanes of a row combine by a fixed
+// butterfly (deterministic order).
+constexpr int NI_LANES = 8;
+constexpr int NI_DEPTH = 4;
+
+template <int LANES>
+__device__ __forceinline__ double row_neighbour_sum(const int32_t *__restrict__ icolidx,
+                                                    const float *__restrict__ s32, int64_t beg,
+                                                    int64_t end, int l) {
+    double r = 0.0;
+    for (int64_t e0 = beg + l; e0 < end; e0 += (int64_t)LANES * NI_DEPTH) {
+        float v[NI_DEPTH];
+#pragma unroll
+        for (int q = 0; q < NI_DEPTH; ++q) {
+            const int64_t e = e0 + (int64_t)q * LANES;
+            v[q] = e < end ? s32[icolidx[e]] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < NI_DEPTH; ++q) r += (double)v[q];
+    }
+#pragma unroll
+    for (int off = LANES / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, LANES);
+    return r;
+}
+
+__global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N, int64_t n_heavy,
+                                                           int64_t heavy_blocks,
                                                            const int64_t *__restrict__ irowptr,
                                                            const int32_t *__restrict__ icolidx,
                                                            const double *__restrict__ s64,
                                                            const float *__restrict__ s32,
                                                            double tau, double eps,
                                                            float4 *__restrict__ info) {
-    const int64_t k = (int64_t)blockIdx.x * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
-    const int l = threadIdx.x % NI_LANES;
-    const bool live = k < N;
-    double r = 0.0;
-    int64_t beg = 0, end = 0;
-    if (live) {
-        beg = irowptr[k];
-        end = irowptr[k + 1];
-        for (int64_t e = beg + l; e < end; e += NI_LANES) r += (double)s32[icolidx[e]];
+    int64_t k;
+    int l;
+    double r;
+    const int64_t blk = blockIdx.x;
+    if (blk < heavy_blocks) {
+        k = blk * (THREADS / 64) + threadIdx.x / 64;
+        l = threadIdx.x % 64;
+        if (k >= n_heavy) return;   // whole wave leaves together
+        r = row_neighbour_sum<64>(icolidx, s32, irowptr[k], irowptr[k + 1], l);
+    } else {
+        k = n_heavy + (blk - heavy_blocks) * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
+        l = threadIdx.x % NI_LANES;
+        if (k >= N) return;         // whole subgroup leaves together
+        r = row_neighbour_sum<NI_LANES>(icolidx, s32, irowptr[k], irowptr[k + 1], l);
     }
-#pragma unroll
-    for (int off = NI_LANES / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, NI_LANES);
-    if (live && l == 0) {
-        const double dt = dtau_of((double)(end - beg), tau, eps);
+    if (l == 0) {
+        const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
         info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
     }
 }
@@ -281,7 +341,7 @@ struct HopArgs {
     void *Wout;
     const float4 *node;      // (s, sqrt(D_tau), r, 0)
     const float *ab;         // a[D], b[D] of the previous hop's ZNorm
-    double2 *partials;       // [blocks][D] (sum T, sum T^2)
+    double2 *partials;       // [D][blocks] (sum T, sum T^2), column-major
     int64_t N, n_hub, n_med;
     int64_t blk_hub_end, blk_med_end, blocks;
     float alpha, theta;
@@ -451,7 +511,7 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
             t.x += lds_st[ww][tid].x;
             t.y += lds_st[ww][tid].y;
         }
-        a.partials[blk * D + tid] = t;
+        a.partials[(int64_t)tid * a.blocks + blk] = t;
     }
 }
 
@@ -488,11 +548,14 @@ struct FinArgs {
     float *ab;
 };
 
+constexpr int FIN_THREADS = 1024;
+
 __device__ __forceinline__ void finalize_column(const FinArgs &f, int c) {
-    __shared__ double rs[WAVES], rq[WAVES];
+    __shared__ double rs[FIN_THREADS / 64], rq[FIN_THREADS / 64];
     double s = 0.0, q = 0.0;
-    for (int64_t b = threadIdx.x; b < f.blocks; b += THREADS) {
-        const double2 p = f.partials[b * f.D + c];
+    const double2 *col = f.partials + (int64_t)c * f.blocks;
+    for (int64_t b = threadIdx.x; b < f.blocks; b += FIN_THREADS) {
+        const double2 p = col[b];
         s += p.x;
         q += p.y;
     }
@@ -508,8 +571,12 @@ __device__ __forceinline__ void finalize_column(const FinArgs &f, int c) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        s = ((rs[0] + rs[1]) + rs[2]) + rs[3];
-        q = ((rq[0] + rq[1]) + rq[2]) + rq[3];
+        s = 0.0;
+        q = 0.0;
+        for (int i = 0; i < FIN_THREADS / 64; ++i) {
+            s += rs[i];
+            q += rq[i];
+        }
         const double n = (double)f.N;
         const double mu = s / n;
         const double den = n - (double)f.ddof;
@@ -532,7 +599,7 @@ __device__ __forceinline__ void finalize_column(const FinArgs &f, int c) {
     }
 }
 
-__global__ __launch_bounds__(THREADS) void finalize_kernel(const FinArgs f) {
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(const FinArgs f) {
     finalize_column(f, blockIdx.x);
 }
 
@@ -542,7 +609,7 @@ struct FinBatch {
 static_assert(sizeof(FinBatch) <= 3584, "batch table must fit the kernel argument segment");
 
 // grid = (D, graphs)
-__global__ __launch_bounds__(THREADS) void finalize_batch_kernel(const FinBatch fb) {
+__global__ __launch_bounds__(FIN_THREADS) void finalize_batch_kernel(const FinBatch fb) {
     const FinArgs &f = fb.f[blockIdx.y];
     if ((int)blockIdx.x < f.D) finalize_column(f, blockIdx.x);
 }
@@ -785,9 +852,12 @@ ifgp_status launch_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s
 ifgp_status launch_nodeinfo(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
     Scales &sc = h->sc;
     const GraphData &g = h->g;
-    nodeinfo_kernel<<<(unsigned)ceil_div(g.N, THREADS / NI_LANES), THREADS, 0, s>>>(
-        g.N, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(), sc.s64.as<double>(),
-        sc.s32.as<float>(), tau, eps, sc.nodeinfo.as<float4>());
+    const int64_t n_heavy = g.n_hub + g.n_med;
+    const int64_t heavy_blocks = ceil_div(n_heavy, THREADS / 64);
+    const int64_t light_blocks = ceil_div(g.N - n_heavy, THREADS / NI_LANES);
+    nodeinfo_kernel<<<(unsigned)(heavy_blocks + light_blocks), THREADS, 0, s>>>(
+        g.N, n_heavy, heavy_blocks, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
+        sc.s64.as<double>(), sc.s32.as<float>(), tau, eps, sc.nodeinfo.as<float4>());
     IFGP_LAUNCHED();
     sc.tau = tau;
     sc.eps = eps;
@@ -914,7 +984,7 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
             IFGP_LAUNCHED();
             IFGP_TRY(record_event(h, s, false));
             const FinArgs f = make_fin_args(h);
-            finalize_kernel<<<(unsigned)G.Dp, THREADS, 0, s>>>(f);
+            finalize_kernel<<<(unsigned)G.Dp, FIN_THREADS, 0, s>>>(f);
             IFGP_LAUNCHED();
         } else {
             const int m = (int)G.members.size();
@@ -933,7 +1003,7 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
                 IFGP_TRY(launch_hop_batch(bt, bt.start[nb], G.storage, G.Dp, s));
                 IFGP_LAUNCHED();
                 for (int i = 0; i < nb; ++i) IFGP_TRY(record_event(G.members[b0 + i], s, false));
-                finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)nb), THREADS, 0, s>>>(fb);
+                finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)nb), FIN_THREADS, 0, s>>>(fb);
                 IFGP_LAUNCHED();
             }
         }
