@@ -1,0 +1,43 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: DC-SBM N = 2,000,000 (nnz 40M), d = 64, tau = -1, K = 8, BF16 storage.
+
+The FFP is column-separable (each output column depends on the same column of
+the input only), so the FP64 oracle computes a sample of columns exactly,
+which is compared with the same columns of the full-width GPU embedding."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import cref, ffp  # noqa: E402
+from workloads import dcsbm  # noqa: E402
+
+COLS = [0, 1, 2, 3, 29, 63]
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    g = dcsbm(2_000_000, 200, mean_deg=20.0, ratio=2.5, seed=0)
+    rp, ci, _, _ = ffp.canonical_csr(g.src, g.dst, g.N)
+    X = ffp.gaussian_input(g.N, 64, seed=1, cols=COLS)
+    ref = cref.ffp_from_input(rp, ci, g.N, -1.0, 8, X)
+    src = torch.as_tensor(g.src, device="cuda")
+    dst = torch.as_tensor(g.dst, device="cuda")
+    return g, rp, ci, ref, src, dst
+
+
+@pytest.mark.parametrize("storage,tol", [("bf16", 1e-2), ("f16", 1e-2), ("f32", 1e-5)])
+def test_full_size_sampled_columns(big, storage, tol):
+    import paper_2508_19737_amd as ifgp
+    g, rp, ci, ref, src, dst = big
+    G = ifgp.Graph(src, dst, g.N)
+    grp, gci, _ = G.export_csr()
+    assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
+    out = G.embed(-1.0, 8, 64, 1, storage=storage).cpu().numpy()
+    G.destroy()
+    err = ffp.rel_frobenius(out[:, COLS], ref)
+    print(f"2M nodes {storage}: rel_frobenius on columns {COLS} = {err:.3e}", flush=True)
+    assert err <= tol
+    # the remaining columns are well-formed embeddings
+    assert np.all(np.isfinite(out)) and out.min() > 0 and out.max() < 1
