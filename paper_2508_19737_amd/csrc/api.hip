@@ -2,6 +2,7 @@
 // lifecycle, host<->device staging of edge lists, the allocator hook, error
 // strings and hop timing.  Every device step is a kernel in graph.hip,
 // primitives.hip or ffp.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -443,8 +444,9 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
     total += 8 * N + 4 * N + 16 * N;
     // two feature buffers, block statistics (bounded by the row classes:
     // hub rows <= nnz / HUB_DEGREE, medium rows <= nnz / MED_DEGREE), coefficients
+    const int64_t light = std::max<int64_t>(LIGHT_TARGET_BLOCKS, ceil_div(N, light_rows_per_block(1)));
     const int64_t blocks = nnz / HUB_DEGREE + ceil_div(nnz / MED_DEGREE, MED_ROWS_PER_BLOCK) +
-                           ceil_div(N, light_rows_per_block(1)) + 2;
+                           light + 2;
     total += 2 * N * Dp * (int64_t)b + 16 * Dp * blocks + 8 * Dp;
     *bytes = total;
     return IFGP_OK;

@@ -344,6 +344,7 @@ struct HopArgs {
     double2 *partials;       // [D][blocks] (sum T, sum T^2), column-major
     int64_t N, n_hub, n_med;
     int64_t blk_hub_end, blk_med_end, blocks;
+    int light_rows;          // rows per light block (a multiple of 4 * RPW)
     float alpha, theta;
 };
 
@@ -477,9 +478,9 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
         }
     } else {
         // light: one LPR-lane subgroup per row
-        const int64_t row0 = a.n_hub + a.n_med + (blk - a.blk_med_end) * (int64_t)C::LIGHT_ROWS;
-        constexpr int PASSES = C::LIGHT_ROWS / (WAVES * RPW);
-        for (int p = 0; p < PASSES; ++p) {
+        const int64_t row0 = a.n_hub + a.n_med + (blk - a.blk_med_end) * (int64_t)a.light_rows;
+        const int passes = a.light_rows / (WAVES * RPW);
+        for (int p = 0; p < passes; ++p) {
             const int64_t r = row0 + (int64_t)p * WAVES * RPW + w * RPW + g;
             if (r < a.N) {
                 float acc[EPL];
@@ -711,6 +712,7 @@ HopArgs make_hop_args(ifgp_graph_s *h) {
     a.blk_hub_end = g.n_hub;
     a.blk_med_end = g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK);
     a.blocks = hop_blocks(g, j.Dp, j.storage);
+    a.light_rows = light_rows(g, j.Dp, j.storage);
     a.alpha = (float)j.alpha;
     a.theta = (float)j.theta;
     return a;
@@ -811,11 +813,18 @@ ifgp_status record_event(ifgp_graph_s *h, hipStream_t s, bool start) {
 
 }  // namespace
 
+namespace {
+int rows_per_wave(int Dp, int storage) { return 1024 / ((int)dtype_bytes(storage) * Dp); }
+}  // namespace
+
+int light_rows(const GraphData &g, int Dp, int storage) {
+    return light_rows_for(g.N - g.n_hub - g.n_med, rows_per_wave(Dp, storage));
+}
+
 int64_t hop_blocks(const GraphData &g, int Dp, int storage) {
     const int64_t n_light = g.N - g.n_hub - g.n_med;
-    const int rpw = 1024 / ((int)dtype_bytes(storage) * Dp);   // 64 / lanes per row
     return g.n_hub + ceil_div(g.n_med, MED_ROWS_PER_BLOCK) +
-           ceil_div(n_light, light_rows_per_block(rpw));
+           ceil_div(n_light, light_rows(g, Dp, storage));
 }
 
 ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,

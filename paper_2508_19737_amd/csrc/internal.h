@@ -31,10 +31,19 @@ ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int bits, hipStr
 constexpr int64_t HUB_DEGREE = IFGP_HUB_DEGREE;  // >= : one 256-thread block per row
 constexpr int64_t MED_DEGREE = IFGP_MED_DEGREE;  // >= : one wave per row
 constexpr int MED_ROWS_PER_BLOCK = 4;
-// Light rows per block: IFGP_LIGHT_ROWS, or one pass of the block (4 waves
-// of rpw rows each) if that is larger.
+// Light rows per block: at most IFGP_LIGHT_ROWS (or one pass of the block,
+// 4 waves of rpw rows each, if that is larger); fewer for small graphs, so
+// that a hop still launches about LIGHT_TARGET_BLOCKS blocks.
+constexpr int64_t LIGHT_TARGET_BLOCKS = 4096;
 constexpr int light_rows_per_block(int rpw) {
     return IFGP_LIGHT_ROWS > 4 * rpw ? IFGP_LIGHT_ROWS : 4 * rpw;
+}
+inline int light_rows_for(int64_t n_light, int rpw) {
+    const int pass = 4 * rpw, max_passes = light_rows_per_block(rpw) / pass;
+    int64_t passes = (n_light + LIGHT_TARGET_BLOCKS * pass - 1) / (LIGHT_TARGET_BLOCKS * pass);
+    if (passes < 1) passes = 1;
+    if (passes > max_passes) passes = max_passes;
+    return (int)passes * pass;
 }
 
 // Canonical graph plus the execution plan of the hop kernel.
@@ -116,6 +125,7 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
 // Advance every listed job by one hop (one launch per storage/width class).
 ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s);
 int64_t hop_blocks(const GraphData &g, int Dp, int storage);
+int light_rows(const GraphData &g, int Dp, int storage);
 ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
                                   hipStream_t s);
 ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s);
