@@ -509,11 +509,9 @@ IFGP_API ifgp_status ifgp_destroy(ifgp_graph_t g) {
         if (pr.first) (void)hipEventDestroy(pr.first);
         if (pr.second) (void)hipEventDestroy(pr.second);
     }
-    hipStream_t aux = g->aux;
     if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
     if (g->ev_join) (void)hipEventDestroy(g->ev_join);
-    delete g;
-    if (aux) (void)hipStreamDestroy(aux);
+    delete g;   // the auxiliary stream is shared and stays
     return IFGP_OK;
 }
 

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -878,13 +879,31 @@ bool scales_cached(const ifgp_graph_s *h, double tau, double eps) {
     return h->sc.valid && h->sc.tau == tau && h->sc.eps == eps;
 }
 
-// The library-owned stream and events used to overlap independent kernels.
+// Independent kernels overlap on a library-owned stream, one per device,
+// created once and kept for the life of the process; the fork and join
+// events belong to the handle.
+std::mutex g_aux_mu;
+hipStream_t g_aux[64] = {};
+
 ifgp_status ensure_aux(ifgp_graph_s *h) {
-    if (!h->aux) IFGP_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    if (!h->aux) {
+        if (h->device < 0 || h->device >= 64) {
+            set_error("device index out of range");
+            return IFGP_E_DEVICE;
+        }
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        if (!g_aux[h->device])
+            IFGP_HIP(hipStreamCreateWithFlags(&g_aux[h->device], hipStreamNonBlocking));
+        h->aux = g_aux[h->device];
+    }
     if (!h->ev_fork) IFGP_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     if (!h->ev_join) IFGP_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     return IFGP_OK;
 }
+
+// Below this many nodes the random input and the neighbour sums are short
+// and run one after the other on the caller's stream.
+constexpr int64_t OVERLAP_MIN_NODES = 65536;
 }  // namespace
 
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
@@ -937,7 +956,7 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
     j.ddof = p.znorm_ddof;
     j.cur = 0;
     j.out = out;
-    if (fresh_scales && !X) {
+    if (fresh_scales && !X && g.N >= OVERLAP_MIN_NODES) {
         // The random input needs only s; it is arithmetic-bound while the
         // neighbour sums are gather-bound, so run them side by side.
         IFGP_TRY(ensure_aux(h));

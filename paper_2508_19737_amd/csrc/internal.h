@@ -95,7 +95,7 @@ struct Job {
 struct ifgp_graph_s {
     int device = 0;
     hipStream_t stream = nullptr;   // stream of the most recent call
-    hipStream_t aux = nullptr;      // library-owned stream for independent work
+    hipStream_t aux = nullptr;      // library-owned stream (shared per device) for independent work
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ifgp::GraphData g;
     ifgp::Scales sc;

@@ -113,7 +113,7 @@ class Admission:
 
 class Server:
     def __init__(self, max_slots: int = 64, budget_bytes: Optional[int] = None,
-                 build_workers: int = 3, clock: Callable[[], float] = time.perf_counter):
+                 build_workers: int = 4, clock: Callable[[], float] = time.perf_counter):
         import threading
         import torch
         self.torch = torch
@@ -151,9 +151,21 @@ class Server:
         keep_outputs=False each output is released once complete.  Raises
         TimeoutError after max_seconds; `progress` receives a status line
         about once a second."""
-        torch = self.torch
+        import sys
         total = len(requests)
         next_report = 1.0
+        # Build workers need the GIL around each library call; a short switch
+        # interval keeps them from waiting on the scheduling loop.
+        old_interval = sys.getswitchinterval()
+        sys.setswitchinterval(1e-4)
+        try:
+            return self._run(requests, on_done, keep_outputs, max_seconds, progress, total,
+                             next_report)
+        finally:
+            sys.setswitchinterval(old_interval)
+
+    def _run(self, requests, on_done, keep_outputs, max_seconds, progress, total, next_report):
+        torch = self.torch
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         building = []     # (req, cost, future)
         active = []       # (req, cost, graph)
@@ -161,6 +173,7 @@ class Server:
         done = []
         t0 = self.clock()
         while pending or self.adm.queue or building or active or finishing:
+            moved = False
             now = self.clock() - t0
             if now > max_seconds:
                 raise TimeoutError(f"serving did not finish in {max_seconds} s "
@@ -175,6 +188,7 @@ class Server:
             for r, cost in self.adm.admit():
                 r.t_admit = self.clock() - t0
                 building.append((r, cost, self.pool.submit(self._build, r)))
+                moved = True
             still = []
             for r, cost, fut in building:
                 if fut.done():
@@ -183,10 +197,12 @@ class Server:
                     r.out = G.job_begin(r.tau, r.K, r.d, r.seed, stream=self.main, storage=r.storage)
                     r.t_start = self.clock() - t0
                     active.append((r, cost, G))
+                    moved = True
                 else:
                     still.append((r, cost, fut))
             building = still
             if active:
+                moved = True
                 flags = ifgp.job_step([G for _, _, G in active], stream=self.main)
                 keep = []
                 for (r, cost, G), f in zip(active, flags):
@@ -200,6 +216,7 @@ class Server:
             still = []
             for r, cost, G, ev in finishing:
                 if ev.query():
+                    moved = True
                     r.t_done = self.clock() - t0
                     G.destroy()
                     self.adm.release(cost)
@@ -211,6 +228,8 @@ class Server:
                 else:
                     still.append((r, cost, G, ev))
             finishing = still
+            if not moved:
+                time.sleep(5e-5)     # nothing to launch: let the build workers run
             if not active and not finishing and not self.adm.queue:
                 # idle: wait for a build or the next arrival
                 if building:
