@@ -150,6 +150,8 @@ ifgp_status ensure(Buf &b, size_t bytes, hipStream_t s) {
 namespace {
 
 constexpr int64_t MAX_N = 2147483646;  // ids fit int32 with one spare value
+// From this many edges a build runs its few oversized buckets on the side stream.
+constexpr int64_t BUILD_SIDE_MIN_EDGES = 1 << 19;
 
 ifgp_params resolve(const ifgp_params *p) {
     ifgp_params q;
@@ -228,7 +230,7 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
         return IFGP_E_OOM;
     }
     auto fail = [&](ifgp_status st) {
-        delete h;
+        (void)ifgp_destroy(h);
         return st;
     };
     const hipError_t de = hipGetDevice(&h->device);
@@ -240,7 +242,11 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
     Edges e;
     ifgp_status st = stage_edges(src, dst, num_edges, edges_on_device, s, e);
     if (st != IFGP_OK) return fail(st);
-    st = build_graph_device(e.src, e.dst, num_edges, N, s, h->g);
+    if (num_edges >= BUILD_SIDE_MIN_EDGES) {
+        st = ensure_side_stream(h);
+        if (st != IFGP_OK) return fail(st);
+    }
+    st = build_graph_device(e.src, e.dst, num_edges, N, s, h->aux, h->ev_fork, h->ev_join, h->g);
     if (st != IFGP_OK) return fail(st);
     *out = h;
     return IFGP_OK;

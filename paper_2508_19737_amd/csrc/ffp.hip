@@ -906,6 +906,8 @@ ifgp_status ensure_aux(ifgp_graph_s *h) {
 constexpr int64_t OVERLAP_MIN_NODES = 65536;
 }  // namespace
 
+ifgp_status ensure_side_stream(ifgp_graph_s *h) { return ensure_aux(h); }
+
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
     if (scales_cached(h, tau, eps)) return IFGP_OK;
     IFGP_TRY(launch_scales(h, tau, eps, s));

@@ -4,14 +4,16 @@
 //
 //   ingest     validate ids, emit both orientations of every pair as a 64-bit
 //              key (row << B) | col, self-loops as a sentinel past every row
-//   sort       stable LSD radix sort of the keys (primitives.hip)
-//   unique     keep the first of each run of equal keys, drop sentinels
-//   CSR        rowptr by binary search of each row's first key, colidx from the
-//              low bits, degree = row length
+//   bucket     stable LSD radix passes (primitives.hip) over the high bits of
+//              the row only, so keys are grouped in buckets of 2^s rows
+//   per bucket one block sorts the bucket by (row, col) in LDS, keeps the
+//              first of each run of equal keys, drops sentinels, and writes
+//              the survivors' columns and its rows' degrees
+//   CSR        rowptr = prefix sum of the degrees
 //   plan       node order by descending degree (ties by id) and the CSR
 //              relabelled into it: the hop kernel then sees degree-homogeneous
 //              waves, the heavy rows first, and the most gathered rows packed
-//              together
+//              together; the columns move to their CSR place in the same pass
 //   merge      (stream_add) resident keys and increment keys merged by rank,
 //              duplicates dropped, CSR and plan rebuilt
 #include <algorithm>
@@ -271,6 +273,419 @@ __global__ void merge_rank_kernel(const uint64_t *__restrict__ a, int64_t na,
     }
 }
 
+// ---------------------------------------------------------------- bucketed build
+// A fresh build sorts the keys only by the high bits of their row (bucket =
+// row >> s, 2^s consecutive rows per bucket), which takes few device-wide
+// radix passes; one block then sorts, deduplicates and counts each bucket.
+// Inside a bucket a key is ((row mod 2^s) << B) | col, which fits 32 bits.
+constexpr int BK_THREADS = 512;               // bucket_csr_kernel: three blocks per CU
+constexpr int BK_KPL = 16;                    // keys per lane in one LDS pass
+constexpr int BK_CAP = BK_THREADS * BK_KPL;   // largest bucket of bucket_csr_kernel
+constexpr int BK_BIG_THREADS = 1024;          // bucket_big_kernel: one block per CU
+constexpr int BK_BIG_KPL = 24;
+constexpr int BK_SMAX = 9;                    // at most 512 rows per bucket
+constexpr int BK_BINS = 256;
+constexpr uint32_t BK_NONE = 0xFFFFFFFFu;     // self loop or bad id; above every real key
+constexpr int64_t BK_BIG_BLOCKS = 64;         // blocks striding over the oversized buckets
+
+template <int THREADS, int KPL>
+struct BucketLds {
+    static_assert(THREADS >= BK_BINS && THREADS % 64 == 0, "one thread per digit");
+    static constexpr int threads = THREADS, waves = THREADS / 64, kpl = KPL, cap = THREADS * KPL;
+    uint32_t a[cap];
+    int cnt[waves][BK_BINS];
+    int dstart[BK_BINS + 1];
+    int wsum[waves];
+    int64_t gpos[BK_BINS];
+    int64_t wsum64[BK_BINS / 64];
+    int64_t rstart[1 << BK_SMAX];
+    int64_t rend[1 << BK_SMAX];
+    int64_t red[3][waves];
+};
+
+// Valid lanes of the wave whose 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t match8(unsigned g, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (g >> b) & 1u;
+        const uint64_t bm = __ballot(bit);
+        m &= bit ? bm : ~bm;
+    }
+    return m;
+}
+
+// Stable in-place sort of sh.a[0, rounds * threads) by the digit
+// (a >> shift) & 255 (callers pad with BK_NONE, which sorts last).  Wave w
+// ranks the keys at [w*rounds*64, (w+1)*rounds*64), so key order is (wave,
+// round, lane).  On return sh.dstart[g] is where digit g starts
+// (sh.dstart[256] = rounds * threads).  Begins and ends with a block
+// barrier; all lanes active.
+template <typename Lds>
+__device__ __forceinline__ void lds_digit_pass(Lds &sh, int rounds, int shift) {
+    constexpr int KPL = Lds::kpl;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int base = w * rounds * 64 + lane;
+    const uint64_t lt = __lanemask_lt();
+    for (int i = lane; i < BK_BINS; i += 64) sh.cnt[w][i] = 0;
+    __syncthreads();
+    uint32_t key[KPL];
+    uint32_t rank2[KPL / 2];  // two 16-bit ranks per register (ranks < cap)
+    static_assert(Lds::cap <= 65536 && KPL % 2 == 0, "ranks are packed in 16 bits");
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) key[r] = r < rounds ? sh.a[base + r * 64] : 0;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        if (r % 2 == 0) rank2[r / 2] = 0;
+        if (r < rounds) {  // uniform over the block
+            const unsigned g = (key[r] >> shift) & (BK_BINS - 1);
+            const uint64_t m = match8(g, true);
+            const int below = __popcll(m & lt);
+            const int c = sh.cnt[w][g];
+            // the leader's write follows every lane's read of this wave
+            if (below == 0) sh.cnt[w][g] = c + __popcll(m);
+            rank2[r / 2] |= (uint32_t)(c + below) << (16 * (r % 2));
+        }
+    }
+    __syncthreads();
+    int total = 0, inc = 0;
+    if (tid < BK_BINS) {
+        for (int ww = 0; ww < Lds::waves; ++ww) {
+            const int t = sh.cnt[ww][tid];
+            sh.cnt[ww][tid] = total;
+            total += t;
+        }
+        inc = total;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) sh.wsum[w] = inc;
+    }
+    __syncthreads();
+    if (tid < BK_BINS) {
+        int woff = 0;
+        for (int ww = 0; ww < w; ++ww) woff += sh.wsum[ww];
+        sh.dstart[tid] = woff + inc - total;
+    }
+    if (tid == 0) sh.dstart[BK_BINS] = rounds * Lds::threads;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        if (r < rounds) {
+            const unsigned g = (key[r] >> shift) & (BK_BINS - 1);
+            const int rank = (rank2[r / 2] >> (16 * (r % 2))) & 0xFFFF;
+            sh.a[sh.dstart[g] + sh.cnt[w][g] + rank] = key[r];
+        }
+    }
+    __syncthreads();
+}
+
+// Exclusive scan of sh.gpos[0, 256) in place (every thread calls it).
+template <typename Lds>
+__device__ __forceinline__ void scan_gpos(Lds &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int64_t v = 0, inc = 0;
+    if (tid < BK_BINS) {
+        v = sh.gpos[tid];
+        inc = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) sh.wsum64[w] = inc;
+    }
+    __syncthreads();
+    if (tid < BK_BINS) {
+        int64_t woff = 0;
+        for (int ww = 0; ww < w; ++ww) woff += sh.wsum64[ww];
+        sh.gpos[tid] = woff + inc - v;
+    }
+    __syncthreads();
+}
+
+// Survivors of the sorted local keys src[0, n) (LDS or global): the first of
+// each run of equal keys, sentinels dropped.  Their columns go to out[] in
+// order; row r of the bucket owns survivors [rstart[r], rend[r]).  Every
+// thread calls it.
+template <typename Lds, typename P>
+__device__ __forceinline__ void bucket_survivors(Lds &sh, P src, int64_t n, int B,
+                                                 uint64_t cmask, int32_t *__restrict__ out) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t lt = __lanemask_lt();
+    int64_t kept = 0;
+    for (int64_t c = 0; c < n; c += Lds::threads) {
+        const int64_t i = c + tid;
+        uint32_t k = BK_NONE, prev = BK_NONE, next = BK_NONE;
+        if (i < n) {
+            k = src[i];
+            if (i > 0) prev = src[i - 1];
+            if (i + 1 < n) next = src[i + 1];
+        }
+        const bool valid = k != BK_NONE;
+        const bool keep = valid && (i == 0 || prev != k);
+        const uint32_t row = valid ? k >> B : 0;
+        const bool first = valid && (i == 0 || (prev >> B) != row);
+        const bool last = valid && (next == BK_NONE || (next >> B) != row);
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) sh.wsum[w] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int ww = 0; ww < Lds::waves; ++ww) {
+            before += ww < w ? sh.wsum[ww] : 0;
+            total += sh.wsum[ww];
+        }
+        const int64_t pos = kept + before + __popcll(m & lt);
+        if (keep) out[pos] = (int32_t)(k & cmask);
+        if (first) sh.rstart[row] = pos;
+        if (last) sh.rend[row] = pos + (keep ? 1 : 0);
+        kept += total;
+        __syncthreads();
+    }
+}
+
+// bstart[b] = first key of bucket b (keys sorted by row >> s); bstart[nbk] = n.
+__global__ void bucket_bounds_kernel(const uint64_t *__restrict__ keys, int64_t n, int B, int s,
+                                     int64_t nbk, int64_t *__restrict__ bstart) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbk) return;
+    if (b == nbk) {
+        bstart[b] = n;
+        return;
+    }
+    const uint64_t target = ((uint64_t)b << s) << B;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    bstart[b] = lo;
+}
+
+__device__ __forceinline__ uint32_t local_key(uint64_t k, int64_t N, int B, int s) {
+    const int64_t row = (int64_t)(k >> B);
+    return row >= N ? BK_NONE
+                    : (uint32_t)((((uint64_t)row & (((uint64_t)1 << s) - 1)) << B) |
+                                 (k & (((uint64_t)1 << B) - 1)));
+}
+
+// Degrees of bucket b's rows from sh.rstart/rend, and the block's part of
+// the statistics (as in degree_kernel).  Every thread calls it.
+template <typename Lds>
+__device__ __forceinline__ void bucket_degrees(Lds &sh, int64_t b, int s, int64_t N,
+                                               int32_t *__restrict__ deg,
+                                               int64_t *__restrict__ stats) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int64_t mx = 0, hub = 0, med = 0;
+    for (int r = tid; r < (1 << s); r += Lds::threads) {
+        const int64_t node = (b << s) + r;
+        if (node < N) {
+            const int64_t d = sh.rend[r] - sh.rstart[r];
+            deg[node] = (int32_t)d;
+            mx = d > mx ? d : mx;
+            hub += d >= HUB_DEGREE;
+            med += d >= MED_DEGREE;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+        hub += __shfl_xor(hub, off, 64);
+        med += __shfl_xor(med, off, 64);
+    }
+    if (lane == 0) {
+        sh.red[0][w] = mx;
+        sh.red[1][w] = hub;
+        sh.red[2][w] = med;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int ww = 1; ww < Lds::waves; ++ww) {
+            mx = sh.red[0][ww] > mx ? sh.red[0][ww] : mx;
+            hub += sh.red[1][ww];
+            med += sh.red[2][ww];
+        }
+        if (mx) atomicMax((unsigned long long *)&stats[0], (unsigned long long)mx);
+        if (hub) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)hub);
+        if (med) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)med);
+    }
+}
+
+// Buckets with more than BK_CAP keys, appended to big[] (in no particular
+// order: each is handled on its own).  *nbig counts them.
+__global__ void bucket_big_list_kernel(const int64_t *__restrict__ bstart, int64_t nbk,
+                                       int64_t *__restrict__ big, int64_t *__restrict__ nbig) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbk && bstart[b + 1] - bstart[b] > BK_CAP)
+        big[atomicAdd((unsigned long long *)nbig, 1ull)] = b;
+}
+
+// One block per bucket of at most BK_CAP keys (larger ones are left to
+// bucket_big_kernel): sort its keys by (row, col) in LDS, drop repeats and
+// self loops, write the surviving columns to tcol[bstart[b] ...] in order and
+// the degrees of the bucket's rows.
+__global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void bucket_csr_kernel(
+    const uint64_t *__restrict__ keys, const int64_t *__restrict__ bstart, int64_t N, int B,
+    int s, int32_t *__restrict__ tcol, int32_t *__restrict__ deg, int64_t *__restrict__ stats) {
+    __shared__ BucketLds<BK_THREADS, BK_KPL> sh;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t bs = bstart[b], n64 = bstart[b + 1] - bs;
+    if (n64 > BK_CAP) return;
+    const int n = (int)n64;
+    for (int r = tid; r < (1 << s); r += BK_THREADS) {
+        sh.rstart[r] = 0;
+        sh.rend[r] = 0;
+    }
+    const int rounds = (n + BK_THREADS - 1) / BK_THREADS;  // padded with BK_NONE
+    constexpr int H = BK_KPL / 2;  // two batches of independent loads
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint64_t k[H];
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            const int i = (h * H + r) * BK_THREADS + tid;
+            k[r] = i < n ? keys[bs + i] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            const int i = (h * H + r) * BK_THREADS + tid;
+            if (h * H + r < rounds) sh.a[i] = i < n ? local_key(k[r], N, B, s) : BK_NONE;
+        }
+    }
+    if (rounds > 0)
+        for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
+    bucket_survivors(sh, sh.a, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+    bucket_degrees(sh, b, s, N, deg, stats);
+}
+
+// The buckets listed in big[0, *nbig), a few blocks striding over the list,
+// one block per CU with most of its LDS: a bucket that fits that LDS
+// is handled as in bucket_csr_kernel; a larger one is sorted chunk by chunk
+// through global memory, in its own range of `scratch` (8 bytes per key:
+// room for two 32-bit copies).
+__global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
+    const uint64_t *__restrict__ keys, uint64_t *__restrict__ scratch,
+    const int64_t *__restrict__ bstart, const int64_t *__restrict__ big,
+    const int64_t *__restrict__ nbig, int64_t N, int B, int s, int32_t *__restrict__ tcol,
+    int32_t *__restrict__ deg, int64_t *__restrict__ stats) {
+    using Lds = BucketLds<BK_BIG_THREADS, BK_BIG_KPL>;
+    __shared__ Lds sh;
+    constexpr int CAP = Lds::cap, T = Lds::threads;
+    const int tid = threadIdx.x;
+    const int64_t count = *nbig;
+    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
+        const int64_t b = big[q];
+        const int64_t bs = bstart[b], n = bstart[b + 1] - bs;
+        for (int r = tid; r < (1 << s); r += T) {
+            sh.rstart[r] = 0;
+            sh.rend[r] = 0;
+        }
+        if (n <= CAP) {  // wholly in LDS
+            const int rounds = (int)((n + T - 1) / T);
+            for (int i = tid; i < rounds * T; i += T)
+                sh.a[i] = i < n ? local_key(keys[bs + i], N, B, s) : BK_NONE;
+            for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
+            bucket_survivors(sh, sh.a, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+            bucket_degrees(sh, b, s, N, deg, stats);
+            __syncthreads();
+            continue;
+        }
+        uint32_t *x = reinterpret_cast<uint32_t *>(scratch + bs), *y = x + n;
+        for (int64_t i = tid; i < n; i += T) x[i] = local_key(keys[bs + i], N, B, s);
+        for (int shift = 0; shift < s + B; shift += 8) {
+            for (int i = tid; i < BK_BINS; i += T) sh.gpos[i] = 0;
+            __syncthreads();
+            for (int64_t i = tid; i < n; i += T)
+                atomicAdd((unsigned long long *)&sh.gpos[(x[i] >> shift) & (BK_BINS - 1)], 1ull);
+            __syncthreads();
+            scan_gpos(sh);
+            for (int64_t c0 = 0; c0 < n; c0 += CAP) {
+                const int m = (int)(n - c0 < CAP ? n - c0 : CAP);
+                const int rounds = (m + T - 1) / T, pad = rounds * T - m;
+                // padding (BK_NONE, digit 255) sorts after every key of the chunk
+                for (int i = tid; i < rounds * T; i += T)
+                    sh.a[i] = i < m ? x[c0 + i] : BK_NONE;
+                lds_digit_pass(sh, rounds, shift);
+                for (int i = tid; i < m; i += T) {
+                    const uint32_t k = sh.a[i];
+                    const unsigned g = (k >> shift) & (BK_BINS - 1);
+                    y[sh.gpos[g] + (i - sh.dstart[g])] = k;
+                }
+                __syncthreads();
+                if (tid < BK_BINS)
+                    sh.gpos[tid] += sh.dstart[tid + 1] - sh.dstart[tid] - (tid == BK_BINS - 1 ? pad : 0);
+                __syncthreads();
+            }
+            uint32_t *t = x;
+            x = y;
+            y = t;
+        }
+        __syncthreads();
+        bucket_survivors(sh, x, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+        bucket_degrees(sh, b, s, N, deg, stats);
+        __syncthreads();
+    }
+}
+
+// One block per bucket, after the plan: the bucket's columns (tcol, in row
+// order) become the canonical colidx, and each entry is placed in the
+// relabelled CSR: entry q of row i goes to irowptr[iperm[i]] + q, column
+// iperm[j].  The row of an entry is found by binary search over the
+// bucket's row starts, held in LDS.
+constexpr int FN_THREADS = 256;
+constexpr int FN_ITEMS = 8;  // entries per thread in flight
+__global__ __launch_bounds__(FN_THREADS) void bucket_finish_kernel(
+    const int32_t *__restrict__ tcol, const int64_t *__restrict__ bstart,
+    const int64_t *__restrict__ rowptr, const int32_t *__restrict__ iperm,
+    const int64_t *__restrict__ irowptr, int64_t N, int s, int32_t *__restrict__ colidx,
+    int32_t *__restrict__ icolidx) {
+    __shared__ int64_t lo[(1 << BK_SMAX) + 1];
+    __shared__ int64_t dst[1 << BK_SMAX];
+    const int64_t b = blockIdx.x, r0 = b << s;
+    if (r0 >= N) return;
+    const int nr = (int)((N - r0) < ((int64_t)1 << s) ? (N - r0) : ((int64_t)1 << s));
+    const int64_t p0 = rowptr[r0];
+    for (int r = threadIdx.x; r <= nr; r += FN_THREADS) lo[r] = rowptr[r0 + r] - p0;
+    for (int r = threadIdx.x; r < nr; r += FN_THREADS) dst[r] = irowptr[iperm[r0 + r]];
+    __syncthreads();
+    const int64_t cnt = lo[nr];
+    const int32_t *src = tcol + bstart[b];
+    for (int64_t q0 = 0; q0 < cnt; q0 += FN_THREADS * FN_ITEMS) {
+        int32_t j[FN_ITEMS], v[FN_ITEMS];
+#pragma unroll
+        for (int it = 0; it < FN_ITEMS; ++it) {
+            const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
+            j[it] = q < cnt ? src[q] : 0;
+        }
+#pragma unroll
+        for (int it = 0; it < FN_ITEMS; ++it) {
+            const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
+            if (q < cnt) {
+                colidx[p0 + q] = j[it];
+                v[it] = iperm[j[it]];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < FN_ITEMS; ++it) {
+            const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
+            if (q < cnt) {
+                int a = 0, c = nr;  // lo[a] <= q < lo[c]
+                while (c - a > 1) {
+                    const int mid = (a + c) >> 1;
+                    if (lo[mid] <= q) a = mid;
+                    else c = mid;
+                }
+                icolidx[dst[a] + (q - lo[a])] = v[it];
+            }
+        }
+    }
+}
+
 inline unsigned grid1(int64_t n, int t = T256) { return (unsigned)ceil_div(n, t); }
 
 ifgp_status copy_d2h_sync(void *h, const void *d, size_t bytes, hipStream_t s) {
@@ -315,8 +730,51 @@ ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStrea
     return IFGP_OK;
 }
 
+// The one host synchronisation of a build: counters -> GraphData fields.
+ifgp_status read_counters(const int64_t *ctr, int64_t N, hipStream_t s, GraphData &g) {
+    int64_t h[C_COUNT];
+    IFGP_TRY(copy_d2h_sync(h, ctr, sizeof(h), s));
+    if (h[C_BAD]) {
+        set_error("edge list holds a node id outside [0, %lld)", (long long)N);
+        return IFGP_E_RANGE;
+    }
+    g.nnz = h[C_NNZ];
+    g.self_loops = h[C_LOOPS];
+    g.max_deg = (int32_t)h[C_MAXDEG];
+    g.n_hub = h[C_HUB];
+    g.n_med = h[C_MED] - h[C_HUB];
+    return IFGP_OK;
+}
+
+// Node order by descending degree (ties by id): perm, iperm and the
+// relabelled row pointers irowptr.
+ifgp_status plan_order(int B, hipStream_t s, GraphData &g) {
+    const int64_t N = g.N;
+    const int dbits = bit_width((uint64_t)g.max_deg);
+    Buf ka, kb;
+    IFGP_TRY(alloc(ka, sizeof(uint64_t) * N, s));
+    IFGP_TRY(alloc(kb, sizeof(uint64_t) * N, s));
+    order_keys_kernel<<<grid1(N), T256, 0, s>>>(g.deg.as<int32_t>(), N, g.max_deg, B,
+                                                ka.as<uint64_t>());
+    IFGP_LAUNCHED();
+    uint64_t *sorted = nullptr;
+    IFGP_TRY(radix_sort_u64(ka.as<uint64_t>(), kb.as<uint64_t>(), N, 0, B + dbits, s, &sorted));
+    IFGP_TRY(alloc(g.perm, sizeof(int32_t) * N, s));
+    IFGP_TRY(alloc(g.iperm, sizeof(int32_t) * N, s));
+    Buf ideg;
+    IFGP_TRY(alloc(ideg, sizeof(int32_t) * N, s));
+    perm_kernel<<<grid1(N), T256, 0, s>>>(sorted, N, ((uint64_t)1 << B) - 1, g.deg.as<int32_t>(),
+                                          g.perm.as<int32_t>(), g.iperm.as<int32_t>(),
+                                          ideg.as<int32_t>());
+    IFGP_LAUNCHED();
+    IFGP_TRY(alloc(g.irowptr, sizeof(int64_t) * (N + 1), s));
+    IFGP_TRY(exclusive_scan<int32_t>(ideg.as<int32_t>(), g.irowptr.as<int64_t>(), N,
+                                     g.irowptr.as<int64_t>() + N, s));
+    return IFGP_OK;
+}
+
 // Unique sorted keys (count on the device, at most bound) -> canonical CSR
-// and plan.  The one host synchronisation of a build happens here.
+// and plan (used by the merge of stream_add).
 ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hipStream_t s,
                          int64_t *ctr, GraphData &g) {
     g.N = N;
@@ -335,40 +793,9 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hi
     degree_kernel<<<dgrid, T256, 0, s>>>(g.rowptr.as<int64_t>(), N, g.deg.as<int32_t>(),
                                          ctr + C_MAXDEG);
     IFGP_LAUNCHED();
-    int64_t h[C_COUNT];
-    IFGP_TRY(copy_d2h_sync(h, ctr, sizeof(h), s));
-    if (h[C_BAD]) {
-        set_error("edge list holds a node id outside [0, %lld)", (long long)N);
-        return IFGP_E_RANGE;
-    }
-    const int64_t nnz = h[C_NNZ];
-    g.nnz = nnz;
-    g.self_loops = h[C_LOOPS];
-    g.max_deg = (int32_t)h[C_MAXDEG];
-    g.n_hub = h[C_HUB];
-    g.n_med = h[C_MED] - h[C_HUB];
-
-    // node order by descending degree
-    const int dbits = bit_width((uint64_t)g.max_deg);
-    Buf ka, kb;
-    IFGP_TRY(alloc(ka, sizeof(uint64_t) * N, s));
-    IFGP_TRY(alloc(kb, sizeof(uint64_t) * N, s));
-    order_keys_kernel<<<grid1(N), T256, 0, s>>>(g.deg.as<int32_t>(), N, g.max_deg, B,
-                                                ka.as<uint64_t>());
-    IFGP_LAUNCHED();
-    uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(ka.as<uint64_t>(), kb.as<uint64_t>(), N, B + dbits, s, &sorted));
-    IFGP_TRY(alloc(g.perm, sizeof(int32_t) * N, s));
-    IFGP_TRY(alloc(g.iperm, sizeof(int32_t) * N, s));
-    Buf ideg;
-    IFGP_TRY(alloc(ideg, sizeof(int32_t) * N, s));
-    perm_kernel<<<grid1(N), T256, 0, s>>>(sorted, N, ((uint64_t)1 << B) - 1, g.deg.as<int32_t>(),
-                                          g.perm.as<int32_t>(), g.iperm.as<int32_t>(),
-                                          ideg.as<int32_t>());
-    IFGP_LAUNCHED();
-    IFGP_TRY(alloc(g.irowptr, sizeof(int64_t) * (N + 1), s));
-    IFGP_TRY(exclusive_scan<int32_t>(ideg.as<int32_t>(), g.irowptr.as<int64_t>(), N,
-                                     g.irowptr.as<int64_t>() + N, s));
+    IFGP_TRY(read_counters(ctr, N, s, g));
+    IFGP_TRY(plan_order(B, s, g));
+    const int64_t nnz = g.nnz;
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * nnz, s));
     if (nnz > 0) {
         relabel_kernel<<<grid1(nnz), T256, 0, s>>>(uk, nnz, B, g.rowptr.as<int64_t>(),
@@ -379,26 +806,91 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hi
     return IFGP_OK;
 }
 
+// Rows per bucket of a fresh build: 2^s, with s as large as the 32-bit
+// local key and the row tables allow while the average bucket stays at half
+// of what one block sorts in LDS.
+int bucket_bits(int64_t N, int64_t nkeys, int B) {
+    int s = std::min(std::min(BK_SMAX, B), 32 - B);
+    while (s > 0 && (double)nkeys * (double)((int64_t)1 << s) > (BK_CAP / 2) * (double)N) --s;
+    return s;
+}
+
 }  // namespace
 
 ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
-                               hipStream_t s, GraphData &out) {
+                               hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                               hipEvent_t ev_join, GraphData &out) {
     const int B = bit_width((uint64_t)N);  // holds 0..N (N is the sentinel row)
     Buf ctr;
     IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
     IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
     Buf keys;
     IFGP_TRY(ingest(src, dst, E, N, B, s, keys, ctr.as<int64_t>()));
+    const int64_t n = 2 * E;
+    const int sb = bucket_bits(N, n, B);
+    const int64_t nbk = (N >> sb) + 1;
     Buf tmp;
-    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * 2 * E, s));
+    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
     uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 2 * B, s, &sorted));
-    Buf uk;
-    IFGP_TRY(unique_keys(sorted, 2 * E, B, N, s, uk, ctr.as<int64_t>() + C_NNZ));
+    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted));
+    uint64_t *other = sorted == keys.as<uint64_t>() ? tmp.as<uint64_t>() : keys.as<uint64_t>();
+    Buf bst, tcol;
+    IFGP_TRY(alloc(bst, sizeof(int64_t) * (nbk + 1), s));
+    IFGP_TRY(alloc(tcol, sizeof(int32_t) * n, s));
+    GraphData g;
+    g.N = N;
+    IFGP_TRY(alloc(g.deg, sizeof(int32_t) * N, s));
+    bucket_bounds_kernel<<<grid1(nbk + 1), T256, 0, s>>>(sorted, n, B, sb, nbk,
+                                                          bst.as<int64_t>());
+    IFGP_LAUNCHED();
+    Buf big;
+    IFGP_TRY(alloc(big, sizeof(int64_t) * (nbk + 1), s));
+    int64_t *nbig = big.as<int64_t>() + nbk;
+    IFGP_TRY(fill_i64(nbig, 1, 0, s));
+    bucket_big_list_kernel<<<grid1(nbk), T256, 0, s>>>(bst.as<int64_t>(), nbk, big.as<int64_t>(),
+                                                        nbig);
+    IFGP_LAUNCHED();
+    // The few oversized buckets take long on one block each.  They go first,
+    // on the caller's stream, and the many small buckets beside them on the
+    // side stream, so that the long blocks are placed before the short ones
+    // fill the device.
+    const bool side = aux != nullptr;
+    if (side) {
+        IFGP_HIP(hipEventRecord(ev_fork, s));
+        IFGP_HIP(hipStreamWaitEvent(aux, ev_fork, 0));
+    }
+    bucket_big_kernel<<<(unsigned)BK_BIG_BLOCKS, BK_BIG_THREADS, 0, s>>>(
+        sorted, other, bst.as<int64_t>(), big.as<int64_t>(), nbig, N, B, sb, tcol.as<int32_t>(),
+        g.deg.as<int32_t>(), ctr.as<int64_t>() + C_MAXDEG);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) {
+        bucket_csr_kernel<<<(unsigned)nbk, BK_THREADS, 0, side ? aux : s>>>(
+            sorted, bst.as<int64_t>(), N, B, sb, tcol.as<int32_t>(), g.deg.as<int32_t>(),
+            ctr.as<int64_t>() + C_MAXDEG);
+        le = hipGetLastError();
+    }
+    if (side) {  // joined before anything can return, so no buffer is released early
+        IFGP_HIP(hipEventRecord(ev_join, aux));
+        IFGP_HIP(hipStreamWaitEvent(s, ev_join, 0));
+    }
+    IFGP_HIP(le);
     keys.reset();
     tmp.reset();
-    GraphData g;
-    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), 2 * E, B, N, s, ctr.as<int64_t>(), g));
+    IFGP_TRY(alloc(g.rowptr, sizeof(int64_t) * (N + 1), s));
+    IFGP_TRY(exclusive_scan<int32_t>(g.deg.as<int32_t>(), g.rowptr.as<int64_t>(), N,
+                                     g.rowptr.as<int64_t>() + N, s));
+    IFGP_HIP(hipMemcpyAsync(ctr.as<int64_t>() + C_NNZ, g.rowptr.as<int64_t>() + N,
+                            sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    IFGP_TRY(read_counters(ctr.as<int64_t>(), N, s, g));
+    IFGP_TRY(plan_order(B, s, g));
+    IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * g.nnz, s));
+    IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * g.nnz, s));
+    if (g.nnz > 0) {
+        bucket_finish_kernel<<<(unsigned)nbk, FN_THREADS, 0, s>>>(
+            tcol.as<int32_t>(), bst.as<int64_t>(), g.rowptr.as<int64_t>(), g.iperm.as<int32_t>(),
+            g.irowptr.as<int64_t>(), N, sb, g.colidx.as<int32_t>(), g.icolidx.as<int32_t>());
+        IFGP_LAUNCHED();
+    }
     g.dups = (E - g.self_loops) - g.nnz / 2;
     out = std::move(g);
     return IFGP_OK;
@@ -417,7 +909,7 @@ ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const in
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(uint64_t) * 2 * E, s));
     uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 2 * B, s, &sorted));
+    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 0, 2 * B, s, &sorted));
     Buf inc;
     IFGP_TRY(unique_keys(sorted, 2 * E, B, new_N, s, inc, cinc.as<int64_t>()));
     keys.reset();

@@ -11,9 +11,10 @@ namespace ifgp {
 template <typename In>
 ifgp_status exclusive_scan(const In *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
 ifgp_status fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
-// Sorts n keys whose set bits lie below `bits`; a and b are both n long; on
-// return *sorted is whichever of them holds the ascending result.
-ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int bits, hipStream_t s,
+// Stable sort of n keys by their bits [lo, hi) (bits at and above hi must be
+// zero); a and b are both n long; on return *sorted is whichever of them
+// holds the result.
+ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
                            uint64_t **sorted);
 
 // Row classes of the hop kernel, by degree.  Rows are kept in descending-
@@ -111,14 +112,20 @@ namespace ifgp {
 void release_cached_blocks();
 
 // ---- graph.hip
-// Build the canonical CSR and plan from edges already in device memory.
+// Build the canonical CSR and plan from edges already in device memory.  If
+// aux is given, part of the work runs there, forked from and joined back to
+// s with the two events.
 ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
-                               hipStream_t s, GraphData &out);
+                               hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                               hipEvent_t ev_join, GraphData &out);
 // Merge device edges into `in`, producing `out` (in is left unchanged).
 ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const int64_t *dst,
                                int64_t E, int64_t new_N, hipStream_t s, GraphData &out);
 
 // ---- ffp.hip
+// The library's side stream of h's device (shared, created on first use)
+// and h's fork/join events.
+ifgp_status ensure_side_stream(ifgp_graph_s *h);
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s);
 ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
                       const float *X, const ifgp_params &p, float *out, hipStream_t s);

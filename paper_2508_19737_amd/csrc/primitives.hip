@@ -263,15 +263,15 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
 }
 }  // namespace
 
-ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int bits, hipStream_t s,
+ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
                            uint64_t **sorted) {
     *sorted = a;
-    if (n <= 1 || bits <= 0) return IFGP_OK;
+    if (n <= 1 || hi <= lo) return IFGP_OK;
     const int64_t nb = ceil_div(n, RS_TILE);
     Buf hist;
     IFGP_TRY(alloc(hist, sizeof(int64_t) * RS_BINS * nb, s));
     uint64_t *src = a, *dst = b;
-    for (int shift = 0; shift < bits; shift += RS_BITS) {
+    for (int shift = lo; shift < hi; shift += RS_BITS) {
         radix_hist_kernel<<<nb, RS_THREADS, 0, s>>>(src, n, shift, hist.as<int64_t>(), nb);
         IFGP_LAUNCHED();
         IFGP_TRY(exclusive_scan<int64_t>(hist.as<int64_t>(), hist.as<int64_t>(), RS_BINS * nb,

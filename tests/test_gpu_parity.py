@@ -70,6 +70,21 @@ def csr_cases():
     yield "star", lambda: (np.zeros(9999, np.int64), np.arange(1, 10000), 10000)
     yield "hubs", hub_graph
     yield "ragged_tail", lambda: (*random_edges(4097, 4097 * 3 + 13, 3), 4097)
+    yield "giant_hub", giant_hub_graph
+    yield "dup_heavy", lambda: (*random_edges(8, 100_000, 4, self_loops=0.05, dup=0.9), 8)
+
+
+def giant_hub_graph():
+    """A row of 30,000 neighbours (each edge given twice, once reversed) among
+    random edges: the row's key range is larger than one block sorts in LDS."""
+    rng = np.random.default_rng(11)
+    N = 40_000
+    leaves = rng.permutation(np.arange(1, N))[:30_000]
+    rs, rd = random_edges(N, 60_000, 12, dup=0.2)
+    src = np.concatenate([np.zeros(30_000, np.int64), leaves, rs])
+    dst = np.concatenate([leaves, np.zeros(30_000, np.int64), rd])
+    p = rng.permutation(src.size)
+    return src[p], dst[p], N
 
 
 @pytest.mark.parametrize("name,make", list(csr_cases()))
