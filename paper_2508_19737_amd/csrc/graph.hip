@@ -191,11 +191,12 @@ __global__ __launch_bounds__(T256) void degree_kernel(const int64_t *__restrict_
     }
 }
 
-// key = (max_deg - deg) << B | node: ascending key = descending degree, ties by id
-__global__ void order_keys_kernel(const int32_t *__restrict__ deg, int64_t N, int32_t max_deg,
-                                  int B, uint64_t *__restrict__ keys) {
+// key = (top - deg) << B | node with top >= every degree: ascending key =
+// descending degree, ties by id
+__global__ void order_keys_kernel(const int32_t *__restrict__ deg, int64_t N, int32_t top, int B,
+                                  uint64_t *__restrict__ keys) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) keys[i] = ((uint64_t)(max_deg - deg[i]) << B) | (uint64_t)i;
+    if (i < N) keys[i] = ((uint64_t)(top - deg[i]) << B) | (uint64_t)i;
 }
 
 __global__ void perm_kernel(const uint64_t *__restrict__ keys, int64_t N, uint64_t mask,
@@ -697,6 +698,15 @@ ifgp_status copy_d2h_sync(void *h, const void *d, size_t bytes, hipStream_t s) {
 // Device counters of one build, read back by the single host synchronisation.
 enum { C_LOOPS = 0, C_BAD, C_NNZ, C_MAXDEG, C_HUB, C_MED, C_COUNT };
 
+// Page-locked host slots for the counters, one set per host thread (kept for
+// the thread's life), so that their copy is asynchronous.
+ifgp_status pinned_counters(int64_t **out) {
+    thread_local int64_t *slots = nullptr;
+    if (!slots) IFGP_HIP(hipHostMalloc((void **)&slots, sizeof(int64_t) * C_COUNT, 0));
+    *out = slots;
+    return IFGP_OK;
+}
+
 // Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the device.
 ifgp_status ingest(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
                    hipStream_t s, Buf &keys, int64_t *ctr) {
@@ -730,10 +740,8 @@ ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStrea
     return IFGP_OK;
 }
 
-// The one host synchronisation of a build: counters -> GraphData fields.
-ifgp_status read_counters(const int64_t *ctr, int64_t N, hipStream_t s, GraphData &g) {
-    int64_t h[C_COUNT];
-    IFGP_TRY(copy_d2h_sync(h, ctr, sizeof(h), s));
+// Counters (host copy) -> GraphData fields.
+ifgp_status apply_counters(const int64_t *h, int64_t N, GraphData &g) {
     if (h[C_BAD]) {
         set_error("edge list holds a node id outside [0, %lld)", (long long)N);
         return IFGP_E_RANGE;
@@ -746,19 +754,28 @@ ifgp_status read_counters(const int64_t *ctr, int64_t N, hipStream_t s, GraphDat
     return IFGP_OK;
 }
 
+// The one host synchronisation of a build: counters -> GraphData fields.
+ifgp_status read_counters(const int64_t *ctr, int64_t N, hipStream_t s, GraphData &g) {
+    int64_t h[C_COUNT];
+    IFGP_TRY(copy_d2h_sync(h, ctr, sizeof(h), s));
+    return apply_counters(h, N, g);
+}
+
 // Node order by descending degree (ties by id): perm, iperm and the
-// relabelled row pointers irowptr.
-ifgp_status plan_order(int B, hipStream_t s, GraphData &g) {
+// relabelled row pointers irowptr.  Degrees are below 2^dbits.  The keys
+// (2^dbits - 1 - deg) << B | node start in id order, so a stable sort of
+// the degree bits alone leaves equal degrees in id order.
+ifgp_status plan_order(int B, int dbits, hipStream_t s, GraphData &g) {
     const int64_t N = g.N;
-    const int dbits = bit_width((uint64_t)g.max_deg);
     Buf ka, kb;
     IFGP_TRY(alloc(ka, sizeof(uint64_t) * N, s));
     IFGP_TRY(alloc(kb, sizeof(uint64_t) * N, s));
-    order_keys_kernel<<<grid1(N), T256, 0, s>>>(g.deg.as<int32_t>(), N, g.max_deg, B,
+    order_keys_kernel<<<grid1(N), T256, 0, s>>>(g.deg.as<int32_t>(), N,
+                                                (int32_t)(((int64_t)1 << dbits) - 1), B,
                                                 ka.as<uint64_t>());
     IFGP_LAUNCHED();
     uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(ka.as<uint64_t>(), kb.as<uint64_t>(), N, 0, B + dbits, s, &sorted));
+    IFGP_TRY(radix_sort_u64(ka.as<uint64_t>(), kb.as<uint64_t>(), N, B, B + dbits, s, &sorted));
     IFGP_TRY(alloc(g.perm, sizeof(int32_t) * N, s));
     IFGP_TRY(alloc(g.iperm, sizeof(int32_t) * N, s));
     Buf ideg;
@@ -794,7 +811,7 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hi
                                          ctr + C_MAXDEG);
     IFGP_LAUNCHED();
     IFGP_TRY(read_counters(ctr, N, s, g));
-    IFGP_TRY(plan_order(B, s, g));
+    IFGP_TRY(plan_order(B, bit_width((uint64_t)g.max_deg), s, g));
     const int64_t nnz = g.nnz;
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * nnz, s));
     if (nnz > 0) {
@@ -881,8 +898,22 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
                                      g.rowptr.as<int64_t>() + N, s));
     IFGP_HIP(hipMemcpyAsync(ctr.as<int64_t>() + C_NNZ, g.rowptr.as<int64_t>() + N,
                             sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    IFGP_TRY(read_counters(ctr.as<int64_t>(), N, s, g));
-    IFGP_TRY(plan_order(B, s, g));
+    if (ev_fork) {
+        // The plan needs only the degrees: it is queued before the host waits
+        // for the counters (with a degree bound), so the device keeps working
+        // while the host reads them.
+        int64_t *hc = nullptr;
+        IFGP_TRY(pinned_counters(&hc));
+        IFGP_HIP(hipMemcpyAsync(hc, ctr.as<int64_t>(), sizeof(int64_t) * C_COUNT,
+                                hipMemcpyDeviceToHost, s));
+        IFGP_HIP(hipEventRecord(ev_fork, s));
+        IFGP_TRY(plan_order(B, bit_width((uint64_t)std::min<int64_t>(N - 1, n)), s, g));
+        IFGP_HIP(hipEventSynchronize(ev_fork));
+        IFGP_TRY(apply_counters(hc, N, g));
+    } else {
+        IFGP_TRY(read_counters(ctr.as<int64_t>(), N, s, g));
+        IFGP_TRY(plan_order(B, bit_width((uint64_t)g.max_deg), s, g));
+    }
     IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * g.nnz, s));
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * g.nnz, s));
     if (g.nnz > 0) {
