@@ -38,29 +38,53 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v) {
     return t;
 }
 
-// counters[0] = self-loop pairs, counters[1] = 1 if any id is out of range
+// counters[0] = self-loop pairs, counters[1] = 1 if any id is out of range.
+// Block t takes the RADIX_TILE / 2 edges whose keys form radix tile t; with
+// hist != nullptr it also writes the tile's counts of the digit
+// (key >> hist_shift) & 255 to hist[digit * ntiles + t] (the first pass of
+// radix_sort_u64).
+constexpr int INGEST_EDGES = RADIX_TILE / 2;
 __global__ __launch_bounds__(T256) void ingest_kernel(const int64_t *__restrict__ src,
                                                       const int64_t *__restrict__ dst, int64_t E,
                                                       int64_t N, int B,
                                                       uint64_t *__restrict__ keys,
-                                                      int64_t *__restrict__ counters) {
-    const int64_t e = (int64_t)blockIdx.x * T256 + threadIdx.x;
+                                                      int64_t *__restrict__ counters,
+                                                      int64_t *__restrict__ hist, int hist_shift,
+                                                      int64_t ntiles) {
+    __shared__ int cnt[T256 / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6;
+    if (hist) {
+        for (int i = tid; i < (T256 / 64) * 256; i += T256) (&cnt[0][0])[i] = 0;
+        __syncthreads();
+    }
     int64_t loop = 0, bad = 0;
-    if (e < E) {
-        const int64_t u = src[e], v = dst[e];
-        const uint64_t sent = (uint64_t)N << B;
-        if (u < 0 || u >= N || v < 0 || v >= N) {
-            bad = 1;
-            keys[2 * e] = sent;
-            keys[2 * e + 1] = sent;
-        } else if (u == v) {
-            loop = 1;
-            keys[2 * e] = sent;
-            keys[2 * e + 1] = sent;
-        } else {
-            keys[2 * e] = ((uint64_t)u << B) | (uint64_t)v;
-            keys[2 * e + 1] = ((uint64_t)v << B) | (uint64_t)u;
+    const uint64_t sent = (uint64_t)N << B;
+#pragma unroll 4
+    for (int r = 0; r < INGEST_EDGES / T256; ++r) {
+        const int64_t e = (int64_t)blockIdx.x * INGEST_EDGES + r * T256 + tid;
+        if (e < E) {
+            const int64_t u = src[e], v = dst[e];
+            uint64_t k0 = sent, k1 = sent;
+            if (u < 0 || u >= N || v < 0 || v >= N) bad = 1;
+            else if (u == v) ++loop;
+            else {
+                k0 = ((uint64_t)u << B) | (uint64_t)v;
+                k1 = ((uint64_t)v << B) | (uint64_t)u;
+            }
+            keys[2 * e] = k0;
+            keys[2 * e + 1] = k1;
+            if (hist) {
+                atomicAdd(&cnt[w][(unsigned)(k0 >> hist_shift) & 255u], 1);
+                atomicAdd(&cnt[w][(unsigned)(k1 >> hist_shift) & 255u], 1);
+            }
         }
+    }
+    if (hist) {
+        __syncthreads();
+        int t = 0;
+#pragma unroll
+        for (int ww = 0; ww < T256 / 64; ++ww) t += cnt[ww][tid];
+        hist[(int64_t)tid * ntiles + blockIdx.x] = t;
     }
     loop = block_sum_i64(loop);
     bad = block_sum_i64(bad);
@@ -708,12 +732,17 @@ ifgp_status pinned_counters(int64_t **out) {
 }
 
 // Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the device.
+// Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the
+// device; with hist, the first radix pass's tile counts of the digit at
+// hist_shift (see ingest_kernel).
 ifgp_status ingest(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
-                   hipStream_t s, Buf &keys, int64_t *ctr) {
+                   hipStream_t s, Buf &keys, int64_t *ctr, int64_t *hist = nullptr,
+                   int hist_shift = 0) {
     IFGP_TRY(alloc(keys, sizeof(uint64_t) * 2 * E, s));
     if (E > 0) {
-        ingest_kernel<<<grid1(E), T256, 0, s>>>(src, dst, E, N, B, keys.as<uint64_t>(),
-                                                ctr + C_LOOPS);
+        const int64_t ntiles = ceil_div(2 * E, (int64_t)RADIX_TILE);
+        ingest_kernel<<<(unsigned)ceil_div(E, (int64_t)INGEST_EDGES), T256, 0, s>>>(
+            src, dst, E, N, B, keys.as<uint64_t>(), ctr + C_LOOPS, hist, hist_shift, ntiles);
         IFGP_LAUNCHED();
     }
     return IFGP_OK;
@@ -841,15 +870,21 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
     Buf ctr;
     IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
     IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
-    Buf keys;
-    IFGP_TRY(ingest(src, dst, E, N, B, s, keys, ctr.as<int64_t>()));
     const int64_t n = 2 * E;
     const int sb = bucket_bits(N, n, B);
     const int64_t nbk = (N >> sb) + 1;
+    // the first radix pass's histogram is taken while the keys are made
+    Buf hist;
+    const bool passes = B + sb < 2 * B && n > 1;
+    if (passes) IFGP_TRY(alloc(hist, sizeof(int64_t) * 256 * ceil_div(n, (int64_t)RADIX_TILE), s));
+    Buf keys;
+    IFGP_TRY(ingest(src, dst, E, N, B, s, keys, ctr.as<int64_t>(),
+                    passes ? hist.as<int64_t>() : nullptr, B + sb));
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
     uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted));
+    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted,
+                            passes ? hist.as<int64_t>() : nullptr));
     uint64_t *other = sorted == keys.as<uint64_t>() ? tmp.as<uint64_t>() : keys.as<uint64_t>();
     Buf bst, tcol;
     IFGP_TRY(alloc(bst, sizeof(int64_t) * (nbk + 1), s));

@@ -12,10 +12,14 @@ template <typename In>
 ifgp_status exclusive_scan(const In *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
 ifgp_status fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 // Stable sort of n keys by their bits [lo, hi) (bits at and above hi must be
-// zero); a and b are both n long; on return *sorted is whichever of them
-// holds the result.
+// zero), 8 bits per pass, RADIX_TILE keys per block; a and b are both n
+// long; on return *sorted is whichever of them holds the result.  If
+// first_hist is given it holds the first pass's counts,
+// first_hist[digit * tiles + tile] for digit (key >> lo) & 255, and serves
+// as the histogram buffer (256 * tiles entries).
+constexpr int RADIX_TILE = 4096;
 ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
-                           uint64_t **sorted);
+                           uint64_t **sorted, int64_t *first_hist = nullptr);
 
 // Row classes of the hop kernel, by degree.  Rows are kept in descending-
 // degree order, so each class is a contiguous range of internal rows.

@@ -264,19 +264,25 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
 }  // namespace
 
 ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
-                           uint64_t **sorted) {
+                           uint64_t **sorted, int64_t *first_hist) {
+    static_assert(RS_TILE == RADIX_TILE, "tile of the fused first histogram");
     *sorted = a;
     if (n <= 1 || hi <= lo) return IFGP_OK;
     const int64_t nb = ceil_div(n, RS_TILE);
-    Buf hist;
-    IFGP_TRY(alloc(hist, sizeof(int64_t) * RS_BINS * nb, s));
+    Buf own;
+    int64_t *hist = first_hist;
+    if (!hist) {
+        IFGP_TRY(alloc(own, sizeof(int64_t) * RS_BINS * nb, s));
+        hist = own.as<int64_t>();
+    }
     uint64_t *src = a, *dst = b;
     for (int shift = lo; shift < hi; shift += RS_BITS) {
-        radix_hist_kernel<<<nb, RS_THREADS, 0, s>>>(src, n, shift, hist.as<int64_t>(), nb);
-        IFGP_LAUNCHED();
-        IFGP_TRY(exclusive_scan<int64_t>(hist.as<int64_t>(), hist.as<int64_t>(), RS_BINS * nb,
-                                         nullptr, s));
-        radix_scatter_kernel<<<nb, RS_THREADS, 0, s>>>(src, dst, n, shift, hist.as<int64_t>(), nb);
+        if (!(first_hist && shift == lo)) {
+            radix_hist_kernel<<<nb, RS_THREADS, 0, s>>>(src, n, shift, hist, nb);
+            IFGP_LAUNCHED();
+        }
+        IFGP_TRY(exclusive_scan<int64_t>(hist, hist, RS_BINS * nb, nullptr, s));
+        radix_scatter_kernel<<<nb, RS_THREADS, 0, s>>>(src, dst, n, shift, hist, nb);
         IFGP_LAUNCHED();
         std::swap(src, dst);
     }
