@@ -61,6 +61,13 @@ template <typename T, int D> struct Cfg {
 // ---------------------------------------------------------------- pack/unpack
 __device__ __forceinline__ uint4 ld16(const void *p) { return *reinterpret_cast<const uint4 *>(p); }
 __device__ __forceinline__ void st16(void *p, const uint4 &v) { *reinterpret_cast<uint4 *>(p) = v; }
+// Streaming store (non-temporal hint): a hop's output rows are not read again
+// within the hop, so they should not displace the rows being gathered.
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st16_stream(void *p, const uint4 &v) {
+    const v4u_t x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<v4u_t *>(p));
+}
 
 template <typename T> __device__ __forceinline__ void unpack(const uint4 &r, float *f);
 template <> __device__ __forceinline__ void unpack<float>(const uint4 &r, float *f) {
@@ -407,7 +414,7 @@ __device__ __forceinline__ void row_finish(const HopArgs &a, int64_t r, int sl, 
         const float y = fmaf(a.theta, zself, a.alpha * nd.x * agg);
         wnew[e] = nd.x * tanhf(y);
     }
-    st16((char *)a.Wout + off, pack<T>(wnew, back));
+    st16_stream((char *)a.Wout + off, pack<T>(wnew, back));
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
         const double t = (double)back[e] * (double)nd.y;  // stored T_i (float product, exact in FP64)
