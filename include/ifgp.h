@@ -248,6 +248,61 @@ IFGP_API const char *ifgp_last_error(void);
 /* Library version string. */
 IFGP_API const char *ifgp_version(void);
 
+/* ------------------------------------------------------------------ BIRCH
+ * The clustering step that turns embeddings into a K-agnostic partition
+ * (Sec. III, Algorithm 1 final step; Algorithm 2 fits it partially, to the
+ * embeddings of newly added nodes, for streaming): BIRCH (Zhang,
+ * Ramakrishnan & Livny, SIGMOD 1996) with no preset number of clusters, the
+ * configuration the paper runs (Sec. IV).
+ *
+ *   CF        (n, LS, SS) per entry: count, linear sum, sum of squared norms;
+ *             centroid LS/n, squared radius SS/n - |LS/n|^2
+ *   tree      at most B entries per node (leaves too); inner entries
+ *             summarise their child
+ *   insert    descend to the entry with the nearest centroid (first on
+ *             ties); in the leaf the nearest entry absorbs the point if its
+ *             radius stays <= threshold, else the point is a new entry; an
+ *             overfull node splits around its farthest pair of centroids
+ *             (first pair p < q in row-major order; entries strictly nearer
+ *             to p join p's node, p always does); a root split adds a level
+ *   clusters  the leaf entries, in leaf order (left to right)
+ *   labels    index of the nearest leaf-entry centroid (first on ties)
+ *
+ * All CF arithmetic is FP64.  Distances are compared as |c|^2 - 2 x.c.
+ * Insertion is sequential (each point sees the tree the previous ones left)
+ * and runs on the host; labelling is a dense N x M contraction and runs on
+ * the device.  A BIRCH handle is not thread-safe.
+ */
+typedef struct ifgp_birch_s *ifgp_birch_t;
+
+/* New empty tree for d-dimensional points.  threshold >= 0 (radius),
+ * 2 <= branching_factor <= 1024, 1 <= d <= 1024.  IFGP_E_INVALID otherwise. */
+IFGP_API ifgp_status ifgp_birch_create(int32_t d, double threshold, int32_t branching_factor,
+                                       ifgp_birch_t *out);
+
+/* Insert n points, in row order: Z is n x d row-major FP32 (device memory if
+ * Z_on_device, else host).  A device Z is copied to the host on hip_stream,
+ * which is synchronised. */
+IFGP_API ifgp_status ifgp_birch_partial_fit(ifgp_birch_t b, const float *Z, int64_t n,
+                                            int Z_on_device, void *hip_stream);
+
+/* Points inserted so far, number of clusters (leaf entries), tree height. */
+IFGP_API ifgp_status ifgp_birch_info(ifgp_birch_t b, int64_t *n_points, int64_t *n_clusters,
+                                     int32_t *height);
+
+/* Cluster centroids in leaf order into host memory, n_clusters x d, FP64. */
+IFGP_API ifgp_status ifgp_birch_centers(ifgp_birch_t b, double *centers);
+
+/* labels[i] = index of the nearest cluster centroid to row i of Z (device,
+ * n x d FP32, d <= 64); labels is device int32 n.  Needs at least one
+ * cluster (IFGP_E_STATE otherwise).  The centroids are uploaded (and
+ * hip_stream synchronised) on first use after a change of the tree. */
+IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t n,
+                                        int32_t *labels, void *hip_stream);
+
+/* Release the tree and its device copy (NULL is accepted). */
+IFGP_API ifgp_status ifgp_birch_destroy(ifgp_birch_t b);
+
 #ifdef __cplusplus
 }
 #endif

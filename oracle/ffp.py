@@ -12,7 +12,7 @@ import scipy.sparse as sp
 
 ALPHA = 1.0      # Eq. (2)/(3): InfraredGP's low-pass filter uses (alpha, theta) = (1, 0.1)
 THETA = 0.1
-EPS = 1e-3       # Eq. (1): "epsilon = 0.001 in our experiment"
+EPS = 1e-3       # Eq. (1): the paper sets epsilon to 0.001
 
 
 # ---------------------------------------------------------------------------

@@ -8,8 +8,10 @@ Public API (thin wrappers over the C ABI in include/ifgp.h):
     embed_batch(graphs, ...)      several graphs, hops batched per launch
     Graph.job_begin / job_step    hop-by-hop driving for serving loops
     gaussian_input(N, d, seed)    the random input alone
+    Birch(d, threshold)           BIRCH clustering of the embeddings (host
+                                  CF-tree, device labelling)
 """
-from ._lib import (BF16, F16, F32, F64, EXPORTS, Graph, IfgpError, embed_batch,  # noqa: F401
+from ._lib import (BF16, F16, F32, F64, EXPORTS, Birch, Graph, IfgpError, embed_batch,  # noqa: F401
                    empty_cache, footprint_bytes, gaussian_input, job_step, lib, params, use_hip_allocator,
                    use_torch_allocator, version)
 

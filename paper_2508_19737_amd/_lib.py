@@ -29,6 +29,8 @@ EXPORTS = [
     "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_empty_cache", "ifgp_timing_enable",
     "ifgp_timing_read",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
+    "ifgp_birch_create", "ifgp_birch_partial_fit", "ifgp_birch_info", "ifgp_birch_centers",
+    "ifgp_birch_predict", "ifgp_birch_destroy",
 ]
 
 
@@ -74,6 +76,12 @@ def _load():
         "ifgp_timing_enable": [P, ctypes.c_int],
         "ifgp_timing_read": [P, P, P],
         "ifgp_destroy": [P],
+        "ifgp_birch_create": [i32, f64, i32, ctypes.POINTER(P)],
+        "ifgp_birch_partial_fit": [P, P, i64, ctypes.c_int, P],
+        "ifgp_birch_info": [P, P, P, P],
+        "ifgp_birch_centers": [P, P],
+        "ifgp_birch_predict": [P, P, i64, P, P],
+        "ifgp_birch_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -340,3 +348,78 @@ def gaussian_input(N, d, seed, dtype="f64", out=None, stream=None):
     check(lib.ifgp_gaussian_input(int(N), int(d), ctypes.c_uint64(int(seed)), code,
                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+class Birch:
+    """BIRCH with no preset number of clusters (the clustering step after the
+    FFP; rules in include/ifgp.h).  The CF-tree lives in the library (host);
+    predict runs on the device."""
+
+    def __init__(self, d, threshold, branching_factor=50):
+        self.d = int(d)
+        h = ctypes.c_void_p()
+        check(lib.ifgp_birch_create(self.d, float(threshold), int(branching_factor),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def _live(self):
+        if not self._h:
+            raise IfgpError(E_INVALID, "BIRCH tree already destroyed")
+        return self._h
+
+    def partial_fit(self, Z, stream=None):
+        """Insert the rows of Z (n x d; a torch tensor on the GPU or any host
+        array), in order."""
+        torch = _torch()
+        if isinstance(Z, torch.Tensor) and Z.is_cuda:
+            Zt = Z.detach().to(torch.float32).contiguous()
+            if Zt.dim() != 2 or Zt.shape[1] != self.d:
+                raise IfgpError(E_INVALID, f"Z must be n x {self.d}")
+            check(lib.ifgp_birch_partial_fit(self._live(), ctypes.c_void_p(Zt.data_ptr()),
+                                             Zt.shape[0], 1, _stream_ptr(stream)))
+        else:
+            Zh = np.ascontiguousarray(np.asarray(Z, dtype=np.float32))
+            if Zh.ndim != 2 or Zh.shape[1] != self.d:
+                raise IfgpError(E_INVALID, f"Z must be n x {self.d}")
+            check(lib.ifgp_birch_partial_fit(self._live(), Zh.ctypes.data_as(ctypes.c_void_p),
+                                             Zh.shape[0], 0, None))
+        return self
+
+    def info(self):
+        n = ctypes.c_int64()
+        m = ctypes.c_int64()
+        h = ctypes.c_int32()
+        check(lib.ifgp_birch_info(self._live(), ctypes.byref(n), ctypes.byref(m), ctypes.byref(h)))
+        return {"points": n.value, "clusters": m.value, "height": h.value}
+
+    def centers(self):
+        m = self.info()["clusters"]
+        out = np.empty((m, self.d), dtype=np.float64)
+        check(lib.ifgp_birch_centers(self._live(), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def predict(self, Z, out=None, stream=None):
+        """Labels (device int32) of the rows of Z (a GPU tensor, n x d)."""
+        torch = _torch()
+        Zt = Z.detach().to(torch.float32).contiguous()
+        if Zt.dim() != 2 or Zt.shape[1] != self.d or not Zt.is_cuda:
+            raise IfgpError(E_INVALID, f"Z must be a GPU tensor n x {self.d}")
+        if out is None:
+            out = torch.empty(Zt.shape[0], dtype=torch.int32, device=Zt.device)
+        check(lib.ifgp_birch_predict(self._live(), ctypes.c_void_p(Zt.data_ptr()), Zt.shape[0],
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def fit_predict(self, Z, stream=None):
+        return self.partial_fit(Z, stream).predict(Z, stream=stream)
+
+    def destroy(self):
+        if self._h:
+            check(lib.ifgp_birch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

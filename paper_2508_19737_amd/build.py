@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libifgp.so")
-SOURCES = ["primitives.hip", "graph.hip", "ffp.hip", "api.hip"]
+SOURCES = ["primitives.hip", "graph.hip", "ffp.hip", "api.hip", "birch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,118 @@
+"""BIRCH on the device: labelling (every point against every cluster
+centroid, FP64) against the oracle, and the whole downstream step of
+Algorithm 1 (FFP on the GPU, then BIRCH) and of Algorithm 2 (partial fits of
+new nodes' embeddings) against the oracle on the same embedding.
+
+Labels are integers decided by floating point: both sides decide in FP64;
+where they differ (summation order only), the two candidate distances must
+be equal to rounding, so either label is valid."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import birch, ffp  # noqa: E402
+from workloads import dcsbm  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ifgp():
+    import torch
+    import paper_2508_19737_amd as m
+    assert torch.cuda.is_available()
+    m.use_torch_allocator()
+    return m
+
+
+def check_labels(X, centers, got):
+    """got equals the oracle's argmin, except where the two distances tie to
+    rounding."""
+    want = birch.predict(X, centers)
+    diff = np.flatnonzero(got != want)
+    if diff.size:
+        dist = birch.reduced_distances(X[diff], centers)
+        a = dist[np.arange(diff.size), got[diff]]
+        b = dist[np.arange(diff.size), want[diff]]
+        scale = np.abs(dist).max(axis=1) + 1.0
+        assert np.all(np.abs(a - b) <= 1e-12 * scale), (diff[:5], a[:5], b[:5])
+    return diff.size
+
+
+@pytest.mark.parametrize("n,d,k,thr,B", [(5000, 8, 30, 0.3, 50), (7777, 16, 40, 0.4, 20),
+                                          (3001, 32, 25, 0.5, 50), (2500, 64, 20, 0.8, 50),
+                                          (1000, 5, 10, 0.2, 7)])
+def test_device_labels_match_oracle(ifgp, n, d, k, thr, B):
+    import torch
+    rng = np.random.default_rng(n)
+    c = rng.random((k, d))
+    X = (c[rng.integers(0, k, size=n)] + rng.normal(size=(n, d)) * 0.05).astype(np.float32)
+    b = ifgp.Birch(d, thr, B).partial_fit(X)
+    centers = b.centers()
+    got = b.predict(torch.as_tensor(X, device="cuda")).cpu().numpy()
+    flips = check_labels(X.astype(np.float64), centers, got)
+    log(f"n={n} d={d}: {centers.shape[0]} clusters, {flips} labels decided by rounding")
+    b.destroy()
+
+
+def test_predict_needs_clusters(ifgp):
+    import torch
+    b = ifgp.Birch(8, 0.5)
+    with pytest.raises(ifgp.IfgpError) as e:
+        b.predict(torch.zeros((4, 8), device="cuda"))
+    assert e.value.status == -5
+    b.destroy()
+
+
+@pytest.fixture(scope="module")
+def medium():
+    g = dcsbm(50_000, 44, mean_deg=20.0, ratio=2.5, seed=0)
+    return g
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_static_pipeline(ifgp, medium, storage):
+    """Algorithm 1 end to end on the device path (FFP, then BIRCH fitted and
+    labelled by the library) equals the oracle BIRCH on the same embedding;
+    its NMI against the planted blocks is reported."""
+    from sklearn.metrics import normalized_mutual_info_score as nmi
+    g = medium
+    G = ifgp.Graph(g.src, g.dst, g.N)
+    Z = G.embed(-1.0, 8, 32, 1, storage=storage)
+    G.destroy()
+    b = ifgp.Birch(32, 0.5, 50).partial_fit(Z)
+    got = b.predict(Z).cpu().numpy()
+    Zh = Z.cpu().numpy().astype(np.float64)
+    o = birch.Birch(0.5, 50).fit(Zh)
+    assert np.array_equal(b.centers(), o.centers())
+    flips = check_labels(Zh, o.centers(), got)
+    log(f"{storage}: {b.info()['clusters']} clusters, NMI {nmi(g.labels, got):.4f}, "
+        f"{flips} labels decided by rounding")
+    b.destroy()
+
+
+def test_streaming_partial_fit(ifgp, medium):
+    """Algorithm 2's clustering: after each step the new nodes' embeddings are
+    fitted into the existing tree and all nodes are labelled; the tree equals
+    the oracle's after the same partial fits."""
+    import torch
+    g = medium
+    G = ifgp.Graph(g.src, g.dst, g.N)
+    Z = G.embed(-1.0, 8, 32, 1)
+    G.destroy()
+    Zh = Z.cpu().numpy().astype(np.float64)
+    b = ifgp.Birch(32, 0.5, 50)
+    o = birch.Birch(0.5, 50)
+    for lo in range(0, g.N, 12_500):
+        b.partial_fit(Z[lo:lo + 12_500])
+        o.partial_fit(Zh[lo:lo + 12_500])
+        assert np.array_equal(b.centers(), o.centers())
+        got = b.predict(Z[:lo + 12_500]).cpu().numpy()
+        check_labels(Zh[:lo + 12_500], o.centers(), got)
+    b.destroy()
