@@ -128,6 +128,55 @@ def bench_streaming(ifgp, say, reps=20):
             "per_increment_mean_ms": [float(x) for x in lat.reshape(reps, 10).mean(axis=0)]}
 
 
+def bench_birch(ifgp, say):
+    """The clustering step after the FFP (Alg. 1, last step): the BF16
+    embedding (d=32, tau=-1, K=8) of the 200,000-node streaming graph is
+    clustered by BIRCH (threshold 0.5, branching factor 50, no preset number
+    of clusters).  The CF-tree is built on the host (sequential insertion);
+    labelling, every point against every cluster centroid in FP64, runs on
+    the device and is timed with HIP events on its stream.  The FP64 oracle
+    tree is timed on the first 20,000 points for comparison."""
+    import torch
+    from oracle import birch as obirch
+    from workloads import dcsbm
+    say("birch: N=200000, d=32")
+    g = dcsbm(200_000, 100, mean_deg=20.0, ratio=2.5, seed=0)
+    G = ifgp.Graph(g.src, g.dst, g.N)
+    Z = G.embed(-1.0, 8, 32, 1, storage="bf16")
+    G.destroy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = ifgp.Birch(32, 0.5, 50).partial_fit(Z)
+    fit_s = time.perf_counter() - t0
+    M = b.info()["clusters"]
+    labels = b.predict(Z)                         # uploads the centroids
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ev0.record(stream)
+    for _ in range(reps):
+        b.predict(Z, out=labels)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    pred_ms = ev0.elapsed_time(ev1) / reps
+    flops = 2.0 * g.N * M * 32
+    b.destroy()
+    Zh = Z[:20_000].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    obirch.Birch(0.5, 50).fit(Zh)
+    oracle_s = time.perf_counter() - t0
+    return {"workload": "BIRCH(threshold 0.5, branching 50) on the BF16 FFP embedding (d=32, "
+                        "tau=-1, K=8) of DC-SBM N=200000 B=100 mean degree 20",
+            "clusters": int(M), "fit_host_s": fit_s, "fit_points_per_s": g.N / fit_s,
+            "predict_ms": pred_ms,
+            "predict_roofline": {"bound": "alu", "achieved": flops / (pred_ms * 1e-3) / 1e12,
+                                 "peak": 78.6, "unit": "TFLOP/s",
+                                 "frac": flops / (pred_ms * 1e-3) / 1e12 / 78.6,
+                                 "flops": flops, "precision": "fp64"},
+            "oracle_fit_points_per_s": 20_000 / oracle_s,
+            "oracle_sample": "FP64 NumPy oracle tree on the first 20,000 points, 1 core"}
+
+
 def bench_serving(a, say):
     """Serving mix: requests draw DC-SBM graphs (N log-uniform in [1e3, 5e5],
     blocks ~ N^0.33, mean degree U[10,30], ratio U[2,5]) from a seeded pool;
@@ -186,6 +235,7 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--no-birch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -282,6 +332,7 @@ def main():
 
     del graphs, G
     streaming = None if a.no_streaming else bench_streaming(ifgp, say)
+    birch = None if a.no_birch else bench_birch(ifgp, say)
     serving = None if a.no_serving else bench_serving(a, say)
 
     work = nnz * a.d * a.K
@@ -313,6 +364,7 @@ def main():
                      "achieved_compulsory": comp},
         "cpu_baseline": cpu,
         "streaming": streaming,
+        "birch": birch,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
