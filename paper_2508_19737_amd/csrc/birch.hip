@@ -9,10 +9,8 @@
 //           touches at most B entries per level, so it stays on the host in
 //           FP64 (rules in ifgp.h).
 //   device  labelling: every point against every leaf-entry centroid, a
-//           dense N x M x d contraction with an argmin, in FP64 (the same
-//           precision as the tree's own decisions).  On gfx950 FP64 vector
-//           FMA runs at the FP64 matrix-core rate, so a plain register/LDS
-//           tiled kernel reaches the same peak without MFMA.
+//           dense N x M x d contraction with an argmin, on the FP64 matrix
+//           cores (the same precision as the tree's own decisions).
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -226,45 +224,97 @@ int64_t count_clusters(const ifgp_birch_s *t) {
 }
 
 // ---------------------------------------------------------------- labelling
-// One thread per point, its coordinates in registers (FP64); the centroids
-// pass through LDS in tiles of CT (read as broadcasts: every lane reads the
-// same centroid).  Centroids are stored zero padded to Dp columns, points are
-// read for their d columns only.
-constexpr int PT = 256;
-constexpr int CT = 64;
+// Distances of points to centroids are a dense contraction, done on the FP64
+// matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 block A (16 points,
+// 4 coordinates) by a 4 x 16 block B (4 coordinates, 16 centroids).  Lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; the 16 x 16 result D[i][j]
+// is in lane j + 16 (i % 4), slot i / 4 (checked on the device).
+//
+// One wave takes 16 * RB points (RB blocks of 16 rows, their coordinates in
+// registers for the whole run) and streams every centroid block's B
+// fragments from memory, the next block's while the current one multiplies.
+// Each lane keeps the best centroid of its column for each of its rows;
+// the 16 lanes of a row group agree at the end (first index on ties).
+// Centroids are stored on the device as fragments: for block cb of 16
+// centroids and coordinate step s, 64 doubles in lane order; the centroid
+// count is padded to a multiple of 16 with zero centroids of norm +inf.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int LW = 4;  // waves per block
 
-template <int Dp>
-__global__ __launch_bounds__(PT) void birch_label_kernel(const float *__restrict__ Z, int64_t n,
-                                                         int d, const double *__restrict__ C,
-                                                         const double *__restrict__ cn,
-                                                         int64_t M, int32_t *__restrict__ labels) {
-    __shared__ double tile[CT][Dp];
-    __shared__ double tnorm[CT];
-    const int64_t i = (int64_t)blockIdx.x * PT + threadIdx.x;
-    const bool live = i < n;
-    double z[Dp];
+template <int Dp, int RB>
+__global__ __launch_bounds__(64 * LW) void birch_label_kernel(const float *__restrict__ Z,
+                                                              int64_t n, int d,
+                                                              const double *__restrict__ F,
+                                                              const double *__restrict__ cn,
+                                                              int64_t nblk,
+                                                              int32_t *__restrict__ labels) {
+    constexpr int S = Dp / 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int64_t p0 = ((int64_t)blockIdx.x * LW + (threadIdx.x >> 6)) * (16 * RB);
+    if (p0 >= n) return;  // the whole wave
+    double a[RB][S];
 #pragma unroll
-    for (int k = 0; k < Dp; ++k) z[k] = (live && k < d) ? (double)Z[i * d + k] : 0.0;
-    double best = 0.0;
-    int64_t bi = 0;
-    for (int64_t c0 = 0; c0 < M; c0 += CT) {
-        const int m = (int)(M - c0 < CT ? M - c0 : CT);
-        __syncthreads();
-        for (int e = threadIdx.x; e < m * Dp; e += PT) tile[e / Dp][e % Dp] = C[c0 * Dp + e];
-        for (int e = threadIdx.x; e < m; e += PT) tnorm[e] = cn[c0 + e];
-        __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four chains: k mod 4
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int k = 0; k < Dp; ++k) acc[k % 4] = fma(z[k], tile[j][k], acc[k % 4]);
-            const double dj = tnorm[j] - 2.0 * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
-            if ((c0 == 0 && j == 0) || dj < best) {
-                best = dj;
-                bi = c0 + j;
+        for (int s = 0; s < S; ++s) {
+            const int64_t p = p0 + 16 * rb + col;
+            const int k = 4 * s + grp;
+            a[rb][s] = (p < n && k < d) ? (double)Z[p * d + k] : 0.0;
+        }
+    double best[RB][4];
+    int32_t bi[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            best[rb][r] = __builtin_inf();
+            bi[rb][r] = 0;
+        }
+    double b[S], bn[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) b[s] = F[(int64_t)s * 64 + lane];
+    for (int64_t cb = 0; cb < nblk; ++cb) {
+        if (cb + 1 < nblk)
+#pragma unroll
+            for (int s = 0; s < S; ++s) bn[s] = F[((cb + 1) * S + s) * 64 + lane];
+        const double nrm = cn[cb * 16 + col];
+        const int32_t c = (int32_t)(cb * 16 + col);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][s], b[s], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double dist = nrm - 2.0 * acc[r];
+                if (dist < best[rb][r]) {
+                    best[rb][r] = dist;
+                    bi[rb][r] = c;
+                }
             }
         }
+#pragma unroll
+        for (int s = 0; s < S; ++s) b[s] = bn[s];
     }
-    if (live) labels[i] = (int32_t)bi;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double v = best[rb][r];
+            int32_t i = bi[rb][r];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const double ov = __shfl_xor(v, off, 64);
+                const int32_t oi = __shfl_xor(i, off, 64);
+                if (ov < v || (ov == v && oi < i)) {
+                    v = ov;
+                    i = oi;
+                }
+            }
+            const int64_t p = p0 + 16 * rb + 4 * r + grp;
+            if (col == 0 && p < n) labels[p] = i;
+        }
 }
 
 int padded_dim(int d) {
@@ -275,14 +325,18 @@ int padded_dim(int d) {
 
 ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
     if (!t->dirty) return IFGP_OK;
-    const int d = t->d, Dp = padded_dim(d);
-    const int64_t M = t->clusters;
-    std::vector<double> h((size_t)M * Dp + (size_t)M, 0.0);
+    const int d = t->d, Dp = padded_dim(d), S = Dp / 4;
+    const int64_t M = t->clusters, nblk = ceil_div(M, (int64_t)16), Mp = nblk * 16;
+    std::vector<double> h((size_t)Mp * Dp + (size_t)Mp, 0.0);
+    double *frag = h.data(), *nrm = h.data() + (size_t)Mp * Dp;
+    for (int64_t m = M; m < Mp; ++m) nrm[m] = INFINITY;
     int64_t m = 0;
     for (const BNode *l = t->first_leaf; l; l = l->next_leaf)
         for (int k = 0; k < l->size(); ++k, ++m) {
-            std::memcpy(&h[(size_t)m * Dp], &l->c[(size_t)k * d], sizeof(double) * d);
-            h[(size_t)M * Dp + m] = l->cn[k];
+            const int64_t cb = m / 16, col = m % 16;
+            for (int j = 0; j < d; ++j)  // coordinate j = 4 s + grp -> lane col + 16 grp
+                frag[((size_t)cb * S + j / 4) * 64 + col + 16 * (j % 4)] = l->c[(size_t)k * d + j];
+            nrm[m] = l->cn[k];
         }
     IFGP_TRY(ensure(t->centers, sizeof(double) * h.size(), s));
     IFGP_HIP(hipMemcpyAsync(t->centers.p, h.data(), sizeof(double) * h.size(),
@@ -396,18 +450,22 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
     }
     const hipStream_t s = (hipStream_t)hip_stream;
     IFGP_TRY(upload_centers(b, s));
-    const double *C = b->centers.as<double>();
-    const double *cn = C + b->clusters * b->Dp;
-    const unsigned grid = (unsigned)ceil_div(n, (int64_t)PT);
+    const int64_t nblk = ceil_div(b->clusters, (int64_t)16);
+    const double *F = b->centers.as<double>();
+    const double *cn = F + nblk * 16 * b->Dp;
+#define IFGP_LABEL(DP, RB)                                                                  \
+    birch_label_kernel<DP, RB><<<(unsigned)ceil_div(n, (int64_t)16 * RB * LW), 64 * LW, 0, s>>>( \
+        Z, n, b->d, F, cn, nblk, labels)
     switch (b->Dp) {
-    case 8: birch_label_kernel<8><<<grid, PT, 0, s>>>(Z, n, b->d, C, cn, b->clusters, labels); break;
-    case 16: birch_label_kernel<16><<<grid, PT, 0, s>>>(Z, n, b->d, C, cn, b->clusters, labels); break;
-    case 32: birch_label_kernel<32><<<grid, PT, 0, s>>>(Z, n, b->d, C, cn, b->clusters, labels); break;
-    case 64: birch_label_kernel<64><<<grid, PT, 0, s>>>(Z, n, b->d, C, cn, b->clusters, labels); break;
+    case 8: IFGP_LABEL(8, 4); break;
+    case 16: IFGP_LABEL(16, 4); break;
+    case 32: IFGP_LABEL(32, 4); break;
+    case 64: IFGP_LABEL(64, 2); break;
     default:
         set_error("ifgp_birch_predict: device labelling supports d <= 64");
         return IFGP_E_INVALID;
     }
+#undef IFGP_LABEL
     IFGP_LAUNCHED();
     return IFGP_OK;
 }
