@@ -116,3 +116,49 @@ def test_streaming_partial_fit(ifgp, medium):
         got = b.predict(Z[:lo + 12_500]).cpu().numpy()
         check_labels(Zh[:lo + 12_500], o.centers(), got)
     b.destroy()
+
+
+def test_streaming_gp_algorithm2(ifgp):
+    """Algorithm 2 end to end (snowball model): nodes arrive in batches with
+    their edges to earlier nodes; each step merges the new topology, runs
+    the FFP on the cumulative graph, partially fits BIRCH to the new nodes'
+    embeddings only, appends them to the embeddings kept from earlier steps
+    and labels every node so far.  The same steps taken by the oracle (FP64
+    FFP, oracle BIRCH) give partitions of the same quality (NMI against the
+    planted blocks within 0.01 at every step)."""
+    import torch
+    from sklearn.metrics import normalized_mutual_info_score as nmi
+    from oracle import cref
+    g = dcsbm(20_000, 25, mean_deg=20.0, ratio=2.5, seed=4)
+    rank = np.argsort(np.random.default_rng(1).permutation(g.N))   # arrival order
+    src, dst, lab = rank[g.src], rank[g.dst], np.empty(g.N, np.int64)
+    lab[rank] = g.labels
+    cut = [0, 5000, 10_000, 15_000, 20_000]
+    tau, K, d, thr = -1.0, 8, 32, 0.5
+    G = None
+    b = ifgp.Birch(d, thr, 50)
+    ob = birch.Birch(thr, 50)
+    kept, kept_ref = [], []
+    for t in range(1, len(cut)):
+        n_t = cut[t]
+        new = (np.maximum(src, dst) < n_t) & (np.maximum(src, dst) >= cut[t - 1])
+        if G is None:
+            G = ifgp.Graph(src[new], dst[new], n_t)
+        else:
+            G.stream_add(src[new], dst[new], new_N=n_t)
+        Zt = G.embed(tau, K, d, 1)[cut[t - 1]:n_t]
+        b.partial_fit(Zt)
+        kept.append(Zt)
+        got = b.predict(torch.cat(kept)).cpu().numpy()
+        cum = np.maximum(src, dst) < n_t
+        rp, ci, _, _ = ffp.canonical_csr(src[cum], dst[cum], n_t)
+        ref = cref.ffp_from_input(rp, ci, n_t, tau, K, cref.gaussian_input(n_t, d, 1))
+        ob.partial_fit(ref[cut[t - 1]:n_t])
+        kept_ref.append(ref[cut[t - 1]:n_t])
+        want = ob.predict(np.vstack(kept_ref))
+        n_g, n_o = nmi(lab[:n_t], got), nmi(lab[:n_t], want)
+        log(f"step {t}: {n_t} nodes, {b.info()['clusters']} / {ob.centers().shape[0]} clusters, "
+            f"NMI gpu {n_g:.4f} oracle {n_o:.4f}")
+        assert abs(n_g - n_o) <= 0.01
+    G.destroy()
+    b.destroy()
