@@ -126,7 +126,10 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
  *           u = ((w >> 11) + 0.5) 2^-53; Box-Muller (Box & Muller 1958) on
  *           (u0, u1) gives columns 4q, 4q+1 as r cos(phi), r sin(phi) with
  *           r = sqrt(-2 ln u0), phi = 2 pi u1, and on (u2, u3) columns 4q+2,
- *           4q+3; every value is divided by sqrt(d)
+ *           4q+3; every value is divided by sqrt(d).  This is evaluated
+ *           in FP64 for FP32 storage; for 2-byte storage (BF16, FP16), whose
+ *           rounding dwarfs FP32's, the uniforms are formed from the top 23
+ *           bits, u = ((w >> 41) + 0.5) 2^-23, and the transform runs in FP32
  *   p       parameters, NULL = ifgp_default_params
  *   out     device, N x d FP32, row-major, caller-owned; row i is node i
  * Errors: IFGP_E_INVALID (d, K, tau not finite, params), IFGP_E_OOM,

@@ -130,6 +130,18 @@ template <typename T> __device__ __forceinline__ T cvt_from_f64(double v) {
 }
 
 // ---------------------------------------------------------------- Philox / Box-Muller
+// Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit multiply-adds
+// (each a single v_mad_u64_u32), the partial products shared by both halves.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+    const uint32_t bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t p0 = (uint64_t)al * bl;
+    const uint64_t t = (uint64_t)al * bh + (p0 >> 32);
+    const uint64_t u = (uint64_t)ah * bl + (uint32_t)t;
+    lo = (u << 32) | (uint32_t)p0;
+    hi = (uint64_t)ah * bh + (t >> 32) + (u >> 32);
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64_t &c2,
                                               uint64_t &c3, uint64_t k0, uint64_t k1) {
     constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -140,8 +152,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64
             k0 += W0;
             k1 += W1;
         }
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, c0, hi0, lo0);
+        mulhilo64(M1, c2, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -168,24 +181,25 @@ __device__ __forceinline__ void gaussian4(uint64_t seed, int64_t i, int64_t q, i
     }
 }
 
-// The same four entries with the Box-Muller step in FP32 (the uniforms keep
-// their 53-bit construction and are rounded to FP32 once).  Used only when
-// the result is stored in a 2-byte type, whose rounding (2^-8 or 2^-11) is far
-// coarser than FP32 arithmetic's.
+// The same four entries for 2-byte storage, whose rounding (2^-8 or 2^-11)
+// is far coarser than FP32 arithmetic's: the uniforms are formed from the
+// words' top 23 bits, u = ((w >> 41) + 0.5) 2^-23 (exact in FP32, inside
+// (0, 1)), and Box-Muller uses the hardware's FP32 instructions: log2
+// (ln u = log2 u * ln 2), square root, and sine and cosine of a fraction of
+// a turn (sin(2 pi u) taken as the turn u).
 __device__ __forceinline__ void gaussian4_f32(uint64_t seed, int64_t i, int64_t q, int d, float *z) {
     uint64_t c0 = (uint64_t)i + 1, c1 = (uint64_t)q, c2 = 0, c3 = 0;
     philox4x64_10(c0, c1, c2, c3, seed, 0);
     const uint64_t w[4] = {c0, c1, c2, c3};
     const float inv = 1.0f / sqrtf((float)d);
+    constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        const float ua = (float)(((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53);
-        const float ub = (float)(((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53);
-        const float r = sqrtf(-2.0f * logf(ua));
-        float sn, cs;
-        sincosf(6.2831853071795864769f * ub, &sn, &cs);
-        z[2 * p] = r * cs * inv;
-        z[2 * p + 1] = r * sn * inv;
+        const float ua = ((float)(uint32_t)(w[2 * p] >> 41) + 0.5f) * 0x1p-23f;
+        const float ub = ((float)(uint32_t)(w[2 * p + 1] >> 41) + 0.5f) * 0x1p-23f;
+        const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(ua)) * inv;
+        z[2 * p] = r * __builtin_amdgcn_cosf(ub);
+        z[2 * p + 1] = r * __builtin_amdgcn_sinf(ub);
     }
 }
 

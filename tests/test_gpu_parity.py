@@ -222,6 +222,19 @@ def test_few_hops(ifgp, config1, K):
     assert ffp.rel_frobenius(got, ref) <= FP32_TOL
 
 
+@pytest.mark.parametrize("storage,tol", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -10)])
+def test_half_storage_noise(ifgp, config1, storage, tol):
+    """K = 0 returns sigma(Z^(0)): the 2-byte storage path's own noise (top
+    23 bits of each word, FP32 Box-Muller) against the oracle's FP64 noise,
+    entry by entry within the storage rounding."""
+    g, rp, ci = config1
+    ref = ffp.sigmoid(ffp.gaussian_input(g.N, 32, 1))
+    got = embed_gpu(ifgp, g.src, g.dst, g.N, -1.0, 0, 32, 1, storage=storage)
+    err = np.abs(got - ref).max()
+    log(f"{storage} K=0 max abs error {err:.2e}")
+    assert err <= tol
+
+
 def test_embed_x_matches_oracle(ifgp, config1):
     import torch
     g_, rp, ci = config1
