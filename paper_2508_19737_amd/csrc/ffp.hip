@@ -684,8 +684,10 @@ __global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
         z[e] = 1.0f / (1.0f + expf(-x));
     }
     float *o = out + (int64_t)perm[k] * d + c0;
-    if ((d & 3) == 0) {
-        *reinterpret_cast<float4 *>(o) = make_float4(z[0], z[1], z[2], z[3]);
+    if ((d & 3) == 0) {  // streaming store: the output is not read again here
+        typedef float f4v_t __attribute__((ext_vector_type(4)));
+        const f4v_t v = {z[0], z[1], z[2], z[3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<f4v_t *>(o));
     } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
