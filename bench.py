@@ -78,6 +78,23 @@ def cpu_info():
     return model
 
 
+def cpu_baseline_parallel(g, rp, ci, tau, K, d, cols):
+    """The plain-C FP64 oracle (OpenMP over rows) on a column sample of the
+    same workload, on every host core it is given (OMP_NUM_THREADS)."""
+    import os
+    from oracle import cref
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    X = cref.gaussian_input(g.N, cols, 1)
+    t0 = time.perf_counter()
+    cref.ffp_from_input(rp, ci, g.N, tau, K, X)
+    t = time.perf_counter() - t0
+    nnz = int(rp[-1])
+    return {"value": nnz * cols * K / t, "unit": "nnz*d*K/s", "cores": threads,
+            "kind": "oracle (C, OpenMP)",
+            "sample": f"plain-C FP64 oracle ({K} hops, sigmoid) on {cols} columns of the same graph; "
+                      f"{t:.1f} s"}
+
+
 def cpu_baseline(g, rp, ci, tau, K, d, cols):
     """The FP64 oracle, as it stands, on a column sample of the same workload
     (the FFP is column-separable: each column's output depends on that column
@@ -323,11 +340,13 @@ def main():
     achieved = bytes_hop / (hop_ms_avg * 1e-3) / 1e9
     comp = hop_bytes_compulsory(a.N, nnz, Dp, b, blocks) / (hop_ms_avg * 1e-3) / 1e9
 
-    cpu = None
+    cpu = cpu_par = None
     if not a.no_cpu_baseline:
         say("cpu baseline (oracle)")
         rp_, ci_, _ = G.export_csr()
         cpu = cpu_baseline(g, rp_, ci_.astype(np.int64), a.tau, a.K, a.d, a.cpu_cols)
+        say("cpu baseline (C oracle, all cores)")
+        cpu_par = cpu_baseline_parallel(g, rp_, ci_.astype(np.int64), a.tau, a.K, a.d, 8)
     for x in graphs:
         x.destroy()
 
@@ -364,6 +383,7 @@ def main():
                      "launch_ms": hop_ms_avg, "model": "no gathered row reused from cache",
                      "achieved_compulsory": comp},
         "cpu_baseline": cpu,
+        "cpu_baseline_parallel": cpu_par,
         "streaming": streaming,
         "birch": birch,
         "serving": serving,
