@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -22,6 +23,9 @@
 namespace ifgp {
 namespace {
 
+constexpr int NB = 16;  // entries per block of the coordinate-major centroid copy
+typedef double v4_t __attribute__((ext_vector_type(4)));
+
 struct BNode {
     bool leaf = true;
     std::vector<int64_t> n;   // per entry: points
@@ -29,6 +33,10 @@ struct BNode {
     std::vector<double> ss;   // per entry: sum of squared norms
     std::vector<double> c;    // per entry: centroid ls / n (d)
     std::vector<double> cn;   // per entry: |centroid|^2
+    std::vector<double> ct;   // the centroids again in blocks of NB entries, coordinate-major
+                              // inside a block: entry k, coordinate j at
+                              // ct[((k / NB) * d + j) * NB + k % NB]
+    int cap = 0;              // entries ct has room for (B + 1 rounded up to a block)
     std::vector<BNode *> child;
     BNode *prev_leaf = nullptr, *next_leaf = nullptr;
     int size() const { return (int)n.size(); }
@@ -39,6 +47,81 @@ inline double dot(const double *a, const double *b, int d) {
     for (int k = 0; k < d; ++k) s += a[k] * b[k];
     return s;
 }
+
+// c_k . p for the NB entries of one block at once (the block is NB * d
+// contiguous doubles, coordinate-major): every entry's sum runs over the
+// coordinates in order, exactly as dot() (separate multiply and add, no fused
+// multiply-add), so the result is the same to the last bit; the entries only
+// share the vector lanes.
+__attribute__((always_inline)) inline void dots_block(const double *blk, const double *p, int d,
+                                                      double *out) {
+    v4_t s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double *r = blk + (size_t)j * NB;
+        v4_t c0, c1, c2, c3;
+        std::memcpy(&c0, r, sizeof(v4_t));
+        std::memcpy(&c1, r + 4, sizeof(v4_t));
+        std::memcpy(&c2, r + 8, sizeof(v4_t));
+        std::memcpy(&c3, r + 12, sizeof(v4_t));
+        const v4_t pj = p[j];
+        s0 = s0 + c0 * pj;
+        s1 = s1 + c1 * pj;
+        s2 = s2 + c2 * pj;
+        s3 = s3 + c3 * pj;
+    }
+    std::memcpy(out, &s0, sizeof(v4_t));
+    std::memcpy(out + 4, &s1, sizeof(v4_t));
+    std::memcpy(out + 8, &s2, sizeof(v4_t));
+    std::memcpy(out + 12, &s3, sizeof(v4_t));
+}
+
+__attribute__((always_inline)) inline int nearest_body(const double *ct, const double *cn, int m,
+                                                       const double *p, int d) {
+    double dots[NB];
+    int best = 0;
+    double bd = 0.0;
+    for (int k0 = 0; k0 < m; k0 += NB) {
+        dots_block(ct + (size_t)k0 * d, p, d, dots);
+        const int e = m - k0 < NB ? m - k0 : NB;
+        for (int l = 0; l < e; ++l) {
+            const double dk = cn[k0 + l] - 2.0 * dots[l];
+            if (k0 + l == 0 || dk < bd) {
+                bd = dk;
+                best = k0 + l;
+            }
+        }
+    }
+    return best;
+}
+
+// c_k . p for every entry k < m (out has room for m rounded up to NB).
+__attribute__((always_inline)) inline void dots_body(const double *ct, int m, const double *p,
+                                                     int d, double *out) {
+    for (int k0 = 0; k0 < m; k0 += NB) dots_block(ct + (size_t)k0 * d, p, d, out + k0);
+}
+
+__attribute__((target("avx2"))) int nearest_avx2(const double *ct, const double *cn, int m,
+                                                 const double *p, int d) {
+    return nearest_body(ct, cn, m, p, d);
+}
+__attribute__((target("avx2"))) void dots_avx2(const double *ct, int m, const double *p, int d,
+                                               double *out) {
+    dots_body(ct, m, p, d, out);
+}
+int nearest_base(const double *ct, const double *cn, int m, const double *p, int d) {
+    return nearest_body(ct, cn, m, p, d);
+}
+void dots_base(const double *ct, int m, const double *p, int d, double *out) {
+    dots_body(ct, m, p, d, out);
+}
+
+using nearest_fn = int (*)(const double *, const double *, int, const double *, int);
+using dots_fn = void (*)(const double *, int, const double *, int, double *);
+bool use_avx2() {
+    static const bool yes = __builtin_cpu_supports("avx2");  // known by the first call
+    return yes;
+}
+
 
 }  // namespace
 }  // namespace ifgp
@@ -57,6 +140,7 @@ struct ifgp_birch_s {
     int Dp = 0;
     bool dirty = true;
     int device = -1;
+    bool broken = false;  // a host allocation failed part-way through an insertion
 };
 
 namespace ifgp {
@@ -66,6 +150,15 @@ BNode *new_node(ifgp_birch_s *t, bool leaf) {
     t->pool.emplace_back(new BNode());
     BNode *x = t->pool.back().get();
     x->leaf = leaf;
+    x->cap = (t->B + 1 + NB - 1) / NB * NB;
+    x->ct.assign((size_t)x->cap * t->d, 0.0);
+    // room for B + 1 entries up front: appends never reallocate
+    x->n.reserve(t->B + 1);
+    x->ls.reserve((size_t)(t->B + 1) * t->d);
+    x->ss.reserve(t->B + 1);
+    x->c.reserve((size_t)(t->B + 1) * t->d);
+    x->cn.reserve(t->B + 1);
+    x->child.reserve(t->B + 1);
     return x;
 }
 
@@ -75,6 +168,8 @@ void refresh(BNode *x, int k, int d) {
     const double *ls = &x->ls[(size_t)k * d];
     const double nk = (double)x->n[k];
     for (int j = 0; j < d; ++j) c[j] = ls[j] / nk;
+    double *blk = &x->ct[(size_t)(k / NB) * NB * d + k % NB];
+    for (int j = 0; j < d; ++j) blk[(size_t)j * NB] = c[j];
     x->cn[k] = dot(c, c, d);
 }
 
@@ -100,29 +195,35 @@ void summary(const BNode *x, int d, int64_t &n, std::vector<double> &ls, double 
     }
 }
 
+// Ask for the blocks the next nearest() will read, all at once.
+inline void prefetch_node(const BNode *x, int d) {
+    const char *a = (const char *)x->ct.data();
+    const size_t bytes = (size_t)((x->size() + NB - 1) / NB) * NB * d * sizeof(double);
+    for (size_t o = 0; o < bytes; o += 64) __builtin_prefetch(a + o);
+    const char *c = (const char *)x->cn.data();
+    for (size_t o = 0; o < x->cn.size() * sizeof(double); o += 64) __builtin_prefetch(c + o);
+}
+
+// The entry whose centroid is nearest to p (first on ties), by
+// |c_k|^2 - 2 c_k . p.
 int nearest(const BNode *x, const double *p, int d) {
-    int best = 0;
-    double bd = 0.0;
-    for (int k = 0; k < x->size(); ++k) {
-        const double dk = x->cn[k] - 2.0 * dot(&x->c[(size_t)k * d], p, d);
-        if (k == 0 || dk < bd) {
-            bd = dk;
-            best = k;
-        }
-    }
-    return best;
+    static const nearest_fn impl = use_avx2() ? nearest_avx2 : nearest_base;
+    return impl(x->ct.data(), x->cn.data(), x->size(), p, d);
 }
 
 // Split x around its farthest pair of centroids; a and b replace x (in the
 // leaf order too).
 std::pair<BNode *, BNode *> split(ifgp_birch_s *t, BNode *x) {
     const int d = t->d, k = x->size();
+    static const dots_fn dots = use_avx2() ? dots_avx2 : dots_base;
     std::vector<double> up((size_t)k * k, 0.0);  // squared distances, i < j
+    std::vector<double> row((size_t)x->cap);
     int p = 0, q = 1;
     double far = -1.0;
-    for (int i = 0; i < k; ++i)
+    for (int i = 0; i < k; ++i) {
+        dots(x->ct.data(), k, &x->c[(size_t)i * d], d, row.data());  // c_j . c_i, all j
         for (int j = i + 1; j < k; ++j) {
-            double v = (x->cn[i] + x->cn[j]) - 2.0 * dot(&x->c[(size_t)i * d], &x->c[(size_t)j * d], d);
+            double v = (x->cn[i] + x->cn[j]) - 2.0 * row[j];
             if (v < 0.0) v = 0.0;
             up[(size_t)i * k + j] = v;
             if (v > far) {
@@ -131,6 +232,7 @@ std::pair<BNode *, BNode *> split(ifgp_birch_s *t, BNode *x) {
                 q = j;
             }
         }
+    }
     auto dist = [&](int i, int j) {
         return i == j ? 0.0 : (i < j ? up[(size_t)i * k + j] : up[(size_t)j * k + i]);
     };
@@ -348,6 +450,9 @@ ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
 }
 
 }  // namespace
+
+ifgp_status partial_fit(ifgp_birch_t b, const float *Z, int64_t n, int Z_on_device,
+                        void *hip_stream);
 }  // namespace ifgp
 
 using namespace ifgp;
@@ -370,7 +475,13 @@ IFGP_API ifgp_status ifgp_birch_create(int32_t d, double threshold, int32_t bran
     t->d = d;
     t->T = threshold;
     t->B = branching_factor;
-    t->root = new_node(t, true);
+    try {
+        t->root = new_node(t, true);
+    } catch (const std::bad_alloc &) {
+        delete t;
+        set_error("host allocation failed");
+        return IFGP_E_OOM;
+    }
     t->first_leaf = t->root;
     t->height = 1;
     *out = t;
@@ -383,7 +494,24 @@ IFGP_API ifgp_status ifgp_birch_partial_fit(ifgp_birch_t b, const float *Z, int6
         set_error("ifgp_birch_partial_fit: need a tree, n >= 0 and Z");
         return IFGP_E_INVALID;
     }
+    if (b->broken) {
+        set_error("ifgp_birch_partial_fit: an earlier call ran out of host memory; the tree is unusable");
+        return IFGP_E_STATE;
+    }
     if (n == 0) return IFGP_OK;
+    try {
+        return partial_fit(b, Z, n, Z_on_device, hip_stream);
+    } catch (const std::bad_alloc &) {
+        b->broken = true;
+        set_error("host allocation failed; the tree is unusable (destroy it)");
+        return IFGP_E_OOM;
+    }
+}
+}  // extern "C"
+
+namespace ifgp {
+ifgp_status partial_fit(ifgp_birch_t b, const float *Z, int64_t n, int Z_on_device,
+                        void *hip_stream) {
     const int d = b->d;
     std::vector<float> host;
     const float *src = Z;
@@ -404,6 +532,9 @@ IFGP_API ifgp_status ifgp_birch_partial_fit(ifgp_birch_t b, const float *Z, int6
     b->dirty = true;
     return IFGP_OK;
 }
+}  // namespace ifgp
+
+extern "C" {
 
 IFGP_API ifgp_status ifgp_birch_info(ifgp_birch_t b, int64_t *n_points, int64_t *n_clusters,
                                      int32_t *height) {
@@ -422,6 +553,10 @@ IFGP_API ifgp_status ifgp_birch_centers(ifgp_birch_t b, double *centers) {
         set_error("ifgp_birch_centers: need a tree and an output array");
         return IFGP_E_INVALID;
     }
+    if (b->broken) {
+        set_error("ifgp_birch_centers: an earlier call ran out of host memory; the tree is unusable");
+        return IFGP_E_STATE;
+    }
     int64_t m = 0;
     for (const BNode *l = b->first_leaf; l; l = l->next_leaf) {
         std::memcpy(centers + (size_t)m * b->d, l->c.data(), sizeof(double) * l->c.size());
@@ -436,8 +571,9 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
         set_error("ifgp_birch_predict: need a tree, n >= 0, Z and labels");
         return IFGP_E_INVALID;
     }
-    if (b->clusters == 0) {
-        set_error("ifgp_birch_predict: the tree holds no points");
+    if (b->clusters == 0 || b->broken) {
+        set_error(b->broken ? "ifgp_birch_predict: an earlier call ran out of host memory"
+                            : "ifgp_birch_predict: the tree holds no points");
         return IFGP_E_STATE;
     }
     if (n == 0) return IFGP_OK;
@@ -449,7 +585,12 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
         b->dirty = true;
     }
     const hipStream_t s = (hipStream_t)hip_stream;
-    IFGP_TRY(upload_centers(b, s));
+    try {
+        IFGP_TRY(upload_centers(b, s));
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return IFGP_E_OOM;
+    }
     const int64_t nblk = ceil_div(b->clusters, (int64_t)16);
     const double *F = b->centers.as<double>();
     const double *cn = F + nblk * 16 * b->Dp;
