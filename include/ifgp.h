@@ -285,7 +285,9 @@ IFGP_API ifgp_status ifgp_birch_create(int32_t d, double threshold, int32_t bran
 
 /* Insert n points, in row order: Z is n x d row-major FP32 (device memory if
  * Z_on_device, else host).  A device Z is copied to the host on hip_stream,
- * which is synchronised. */
+ * which is synchronised.  If host memory runs out part-way (IFGP_E_OOM) the
+ * tree is left unusable: later partial_fit, centers and predict calls return
+ * IFGP_E_STATE; info and destroy still work. */
 IFGP_API ifgp_status ifgp_birch_partial_fit(ifgp_birch_t b, const float *Z, int64_t n,
                                             int Z_on_device, void *hip_stream);
 
