@@ -29,15 +29,53 @@ def big():
 
 @pytest.mark.parametrize("storage,tol", [("bf16", 1e-2), ("f16", 1e-2), ("f32", 1e-5)])
 def test_full_size_sampled_columns(big, storage, tol):
+    """Build then embed at once, as bench.py's step does, checked against the
+    oracle's columns; the CSR exported afterwards is the canonical one."""
     import paper_2508_19737_amd as ifgp
     g, rp, ci, ref, src, dst = big
     G = ifgp.Graph(src, dst, g.N)
-    grp, gci, _ = G.export_csr()
-    assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
     out = G.embed(-1.0, 8, 64, 1, storage=storage).cpu().numpy()
+    grp, gci, _ = G.export_csr()
     G.destroy()
+    assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
     err = ffp.rel_frobenius(out[:, COLS], ref)
     print(f"2M nodes {storage}: rel_frobenius on columns {COLS} = {err:.3e}", flush=True)
     assert err <= tol
     # the remaining columns are well-formed embeddings
     assert np.all(np.isfinite(out)) and out.min() > 0 and out.max() < 1
+
+
+def test_call_orders_after_a_build(big):
+    """The same bits for an embed right after the build, after an export,
+    with the build on one stream and the embed on another, and after an edge
+    increment merged straight after a build of half the edges."""
+    import torch
+    import paper_2508_19737_amd as ifgp
+    g, rp, ci, ref, src, dst = big
+    G = ifgp.Graph(src, dst, g.N)
+    a = G.embed(-1.0, 8, 64, 1, storage="bf16").cpu()
+    G.destroy()
+    G = ifgp.Graph(src, dst, g.N)
+    G.export_csr()
+    b = G.embed(-1.0, 8, 64, 1, storage="bf16").cpu()
+    G.destroy()
+    assert torch.equal(a, b)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    G = ifgp.Graph(src, dst, g.N, stream=s1)
+    s2.wait_stream(s1)      # the caller orders its streams; the library orders its own work
+    out = torch.empty((g.N, 64), dtype=torch.float32, device="cuda")
+    out.record_stream(s2)
+    G.embed(-1.0, 8, 64, 1, storage="bf16", out=out, stream=s2)
+    s2.synchronize()
+    assert torch.equal(out.cpu(), a)
+    G.destroy()
+    # an increment right after the build merges into the finished CSR
+    half = g.src.shape[0] // 2
+    G = ifgp.Graph(src[:half], dst[:half], g.N)
+    G.stream_add(src[half:], dst[half:])
+    grp, gci, _ = G.export_csr()
+    assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
+    c = G.embed(-1.0, 8, 64, 1, storage="bf16").cpu()
+    G.destroy()
+    assert torch.equal(c, a)
