@@ -598,10 +598,12 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
     birch_label_kernel<DP, RB><<<(unsigned)ceil_div(n, (int64_t)16 * RB * LW), 64 * LW, 0, s>>>( \
         Z, n, b->d, F, cn, nblk, labels)
     switch (b->Dp) {
-    case 8: IFGP_LABEL(8, 4); break;
-    case 16: IFGP_LABEL(16, 4); break;
-    case 32: IFGP_LABEL(32, 4); break;
-    case 64: IFGP_LABEL(64, 2); break;
+    // one row block per wave: more waves in flight beat more independent
+    // chains per wave (measured for d = 8 ... 64)
+    case 8: IFGP_LABEL(8, 1); break;
+    case 16: IFGP_LABEL(16, 1); break;
+    case 32: IFGP_LABEL(32, 1); break;
+    case 64: IFGP_LABEL(64, 1); break;
     default:
         set_error("ifgp_birch_predict: device labelling supports d <= 64");
         return IFGP_E_INVALID;
