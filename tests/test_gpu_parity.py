@@ -72,6 +72,15 @@ def csr_cases():
     yield "ragged_tail", lambda: (*random_edges(4097, 4097 * 3 + 13, 3), 4097)
     yield "giant_hub", giant_hub_graph
     yield "dup_heavy", lambda: (*random_edges(8, 100_000, 4, self_loops=0.05, dup=0.9), 8)
+    yield "sparse_large_N", sparse_large_graph
+
+
+def sparse_large_graph():
+    """30M nodes (25-bit ids), 6,000 edges: almost every bucket of rows is
+    empty; ids 0 and N - 1 take part."""
+    N = 30_000_000
+    s, d = random_edges(N, 6000, 13, self_loops=0.01, dup=0.2)
+    return np.concatenate([s, [0, N - 1, N - 1]]), np.concatenate([d, [N - 1, 0, 5]]), N
 
 
 def giant_hub_graph():
