@@ -255,7 +255,7 @@ def test_embed_x_matches_oracle(ifgp, config1):
     g.destroy()
 
 
-@pytest.mark.parametrize("case", ["N1", "no_edges", "isolated_tau0", "two_nodes"])
+@pytest.mark.parametrize("case", ["N1", "no_edges", "isolated_tau0", "two_nodes", "sparse_large"])
 def test_degenerate_graphs(ifgp, case):
     if case == "N1":
         src, dst, N = np.zeros(0, np.int64), np.zeros(0, np.int64), 1
@@ -264,13 +264,17 @@ def test_degenerate_graphs(ifgp, case):
     elif case == "isolated_tau0":
         src, dst = random_edges(200, 150, 4)
         N = 260
+    elif case == "sparse_large":     # 1M nodes, nearly all isolated, ragged size
+        N = 1_000_003
+        src, dst = random_edges(N, 5000, 6)
     else:
         src, dst, N = np.array([0]), np.array([1]), 2
     rp, ci, _, _ = ffp.canonical_csr(src, dst, N)
     # Two degree-1 nodes at tau = -1 get s^2 = 1/eps = 1000: tanh saturates and
     # FP32 returns exactly +-1 for both rows where FP64 still keeps a spread of
     # ~1e-9 that ZNorm expands to +-1; that case is outside FP32's reach.
-    taus = (0.0,) if case == "two_nodes" else (0.0, -1.0)
+    # (the same holds for the random pairs of the sparse graph)
+    taus = (0.0,) if case in ("two_nodes", "sparse_large") else (0.0, -1.0)
     for tau in taus:
         ref = ffp.ffp_from_input(rp, ci, N, tau, 3, ffp.gaussian_input(N, 8, 2))
         got = embed_gpu(ifgp, src, dst, N, tau, 3, 8, 2)
