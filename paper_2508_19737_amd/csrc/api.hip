@@ -195,6 +195,19 @@ ifgp_status use_device(ifgp_graph_t g) {
     return IFGP_OK;
 }
 
+// One whole embedding on g; on failure g is left with no job in progress.
+ifgp_status run_job(ifgp_graph_t g, double tau, int32_t K, int32_t d, uint64_t seed,
+                    const float *X, const ifgp_params &p, float *out, hipStream_t s) {
+    ifgp_status st = job_begin(g, tau, K, d, seed, X, p, out, s);
+    while (st == IFGP_OK && !g->job.done) {
+        ifgp_graph_s *one = g;
+        st = jobs_step(&one, 1, s);
+    }
+    if (st != IFGP_OK) g->job = Job{};
+    else g->job.active = false;
+    return st;
+}
+
 }  // namespace
 }  // namespace ifgp
 
@@ -258,13 +271,7 @@ IFGP_API ifgp_status ifgp_embed(ifgp_graph_t g, double tau, int32_t K, int32_t d
     IFGP_TRY(use_device(g));
     hipStream_t s = (hipStream_t)hip_stream;
     g->stream = s;
-    IFGP_TRY(job_begin(g, tau, K, d, seed, nullptr, resolve(p), out, s));
-    while (!g->job.done) {
-        ifgp_graph_s *one = g;
-        IFGP_TRY(jobs_step(&one, 1, s));
-    }
-    g->job.active = false;
-    return IFGP_OK;
+    return run_job(g, tau, K, d, seed, nullptr, resolve(p), out, s);
 }
 
 IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t d, const float *X,
@@ -277,13 +284,7 @@ IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t
     IFGP_TRY(use_device(g));
     hipStream_t s = (hipStream_t)hip_stream;
     g->stream = s;
-    IFGP_TRY(job_begin(g, tau, K, d, 0, X, resolve(p), out, s));
-    while (!g->job.done) {
-        ifgp_graph_s *one = g;
-        IFGP_TRY(jobs_step(&one, 1, s));
-    }
-    g->job.active = false;
-    return IFGP_OK;
+    return run_job(g, tau, K, d, 0, X, resolve(p), out, s);
 }
 
 IFGP_API ifgp_status ifgp_gaussian_input(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
@@ -338,16 +339,25 @@ IFGP_API ifgp_status ifgp_embed_batch(ifgp_graph_t *gs, int32_t n, const double 
             }
     }
     hipStream_t s = (hipStream_t)hip_stream;
+    // a failure leaves none of the graphs with a job in progress
+    auto fail = [&](ifgp_status st) {
+        for (int i = 0; i < n; ++i) gs[i]->job = Job{};
+        return st;
+    };
     for (int i = 0; i < n; ++i) {
-        IFGP_TRY(use_device(gs[i]));
-        gs[i]->stream = s;
-        IFGP_TRY(job_begin(gs[i], tau[i], K[i], d[i], seed[i], nullptr, resolve(p), outs[i], s));
+        ifgp_status st = use_device(gs[i]);
+        if (st == IFGP_OK) {
+            gs[i]->stream = s;
+            st = job_begin(gs[i], tau[i], K[i], d[i], seed[i], nullptr, resolve(p), outs[i], s);
+        }
+        if (st != IFGP_OK) return fail(st);
     }
     for (;;) {
         bool more = false;
         for (int i = 0; i < n; ++i) more |= !gs[i]->job.done;
         if (!more) break;
-        IFGP_TRY(jobs_step(gs, n, s));
+        const ifgp_status st = jobs_step(gs, n, s);
+        if (st != IFGP_OK) return fail(st);
     }
     for (int i = 0; i < n; ++i) gs[i]->job.active = false;
     return IFGP_OK;
