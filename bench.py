@@ -195,6 +195,68 @@ def bench_birch(ifgp, say):
             "oracle_sample": "FP64 NumPy oracle tree on the first 20,000 points, 1 core"}
 
 
+def bench_snowball(ifgp, say, steps=10, reps=3):
+    """Algorithm 2 end to end (snowball model) on the 200,000-node graph:
+    nodes arrive in 10 equal batches (arrival order a seeded permutation),
+    each with its edges to earlier nodes.  A step merges the new topology
+    (ifgp_stream_add with new_N > N), re-embeds the cumulative graph
+    (d=32, tau=-1, K=8, BF16), partially fits BIRCH (threshold 0.5) to the
+    new nodes' embeddings, keeps them, and labels every node so far.  Per-step
+    latency with its parts; every input already in device memory."""
+    import torch
+    from workloads import dcsbm
+    say("snowball: N=200000, 10 node batches")
+    g = dcsbm(200_000, 100, mean_deg=20.0, ratio=2.5, seed=0)
+    rank = np.argsort(np.random.default_rng(1).permutation(g.N))
+    src, dst = rank[g.src], rank[g.dst]
+    hi = np.maximum(src, dst)
+    cut = [g.N * t // steps for t in range(steps + 1)]
+    parts = []
+    for t in range(1, steps + 1):
+        m = (hi >= cut[t - 1]) & (hi < cut[t])
+        parts.append((torch.as_tensor(src[m], device="cuda"), torch.as_tensor(dst[m], device="cuda")))
+    d = 32
+    kept = torch.empty((g.N, d), dtype=torch.float32, device="cuda")
+    labels = torch.empty(g.N, dtype=torch.int32, device="cuda")
+    rows = []
+    for rep in range(reps + 1):
+        G, b = None, ifgp.Birch(d, 0.5, 50)
+        torch.cuda.synchronize()
+        for t in range(1, steps + 1):
+            n_t, n_0 = cut[t], cut[t - 1]
+            t0 = time.perf_counter()
+            if G is None:
+                G = ifgp.Graph(*parts[0], n_t)
+            else:
+                G.stream_add(*parts[t - 1], new_N=n_t)
+            Z = G.embed(-1.0, 8, d, 1, storage="bf16")
+            kept[n_0:n_t].copy_(Z[n_0:n_t])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            b.partial_fit(kept[n_0:n_t])
+            t2 = time.perf_counter()
+            b.predict(kept[:n_t], out=labels[:n_t])
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if rep > 0:
+                rows.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2, b.info()["clusters"]))
+        G.destroy()
+        b.destroy()
+    r = np.array(rows) * np.array([1e3, 1e3, 1e3, 1e3, 1.0])
+    per = r.reshape(reps, steps, 5).mean(axis=0)
+    return {"workload": "Alg. 2 snowball: DC-SBM N=200000 B=100 mean degree 20, nodes arrive in 10 "
+                        "batches of 20000 (seeded order) with their edges to earlier nodes; per step "
+                        "stream_add(new_N) + FFP d=32 tau=-1 K=8 bf16 + BIRCH partial fit of the new "
+                        "nodes + labels of all nodes so far",
+            "samples": int(r.shape[0]), "p50_ms": float(np.percentile(r[:, 0], 50)),
+            "p99_ms": float(np.percentile(r[:, 0], 99)),
+            "per_step_mean_ms": {"total": [float(x) for x in per[:, 0]],
+                                 "merge_and_embed": [float(x) for x in per[:, 1]],
+                                 "birch_partial_fit_host": [float(x) for x in per[:, 2]],
+                                 "labels_device": [float(x) for x in per[:, 3]]},
+            "clusters_final": int(per[-1, 4])}
+
+
 def bench_serving(a, say):
     """Serving mix: requests draw DC-SBM graphs (N log-uniform in [1e3, 5e5],
     blocks ~ N^0.33, mean degree U[10,30], ratio U[2,5]) from a seeded pool;
@@ -254,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--no-birch", action="store_true")
+    ap.add_argument("--no-snowball", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -353,6 +416,7 @@ def main():
     del graphs, G
     streaming = None if a.no_streaming else bench_streaming(ifgp, say)
     birch = None if a.no_birch else bench_birch(ifgp, say)
+    snowball = None if a.no_snowball else bench_snowball(ifgp, say)
     serving = None if a.no_serving else bench_serving(a, say)
 
     work = nnz * a.d * a.K
@@ -386,6 +450,7 @@ def main():
         "cpu_baseline_parallel": cpu_par,
         "streaming": streaming,
         "birch": birch,
+        "snowball": snowball,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)

@@ -406,6 +406,9 @@ class Birch:
             raise IfgpError(E_INVALID, f"Z must be a GPU tensor n x {self.d}")
         if out is None:
             out = torch.empty(Zt.shape[0], dtype=torch.int32, device=Zt.device)
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() \
+                or tuple(out.shape) != (Zt.shape[0],):
+            raise ValueError("out must be a contiguous int32 CUDA tensor of shape (n,)")
         check(lib.ifgp_birch_predict(self._live(), ctypes.c_void_p(Zt.data_ptr()), Zt.shape[0],
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
