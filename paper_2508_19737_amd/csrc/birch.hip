@@ -342,6 +342,7 @@ int64_t count_clusters(const ifgp_birch_s *t) {
 // count is padded to a multiple of 16 with zero centroids of norm +inf.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int LW = 4;  // waves per block
+constexpr int64_t LABEL_SPARE = 2;  // zero blocks stored after the last centroid block
 
 template <int Dp, int RB>
 __global__ __launch_bounds__(64 * LW) void birch_label_kernel(const float *__restrict__ Z,
@@ -372,21 +373,26 @@ __global__ __launch_bounds__(64 * LW) void birch_label_kernel(const float *__res
             best[rb][r] = __builtin_inf();
             bi[rb][r] = 0;
         }
-    double b[S], bn[S];
+    // Two register sets take turns: while one block multiplies, the next is
+    // loading into the other (unrolled by two, so the loads a block waits
+    // for are always the older ones).  The spare blocks keep the loads one
+    // and two blocks ahead in bounds, and an odd block count ends on a spare
+    // block, whose +inf distances never win: the loop body has no branch.
+    double bA[S], bB[S], nA, nB;
+    auto load = [&](double *bf, double &nr, int64_t cb) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) b[s] = F[(int64_t)s * 64 + lane];
-    for (int64_t cb = 0; cb < nblk; ++cb) {
-        if (cb + 1 < nblk)
-#pragma unroll
-            for (int s = 0; s < S; ++s) bn[s] = F[((cb + 1) * S + s) * 64 + lane];
-        const double nrm = cn[cb * 16 + col];
+        for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
+        nr = cn[cb * 16 + col];
+        __builtin_amdgcn_sched_barrier(0);  // issued here, not sunk to their use
+    };
+    auto step = [&](const double *bf, double nrm, int64_t cb) {
         const int32_t c = (int32_t)(cb * 16 + col);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][s], b[s], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][s], bf[s], acc, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double dist = nrm - 2.0 * acc[r];
@@ -396,8 +402,13 @@ __global__ __launch_bounds__(64 * LW) void birch_label_kernel(const float *__res
                 }
             }
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) b[s] = bn[s];
+    };
+    load(bA, nA, 0);
+    for (int64_t cb = 0; cb < nblk; cb += 2) {
+        load(bB, nB, cb + 1);
+        step(bA, nA, cb);
+        load(bA, nA, cb + 2);
+        step(bB, nB, cb + 1);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -428,7 +439,9 @@ int padded_dim(int d) {
 ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
     if (!t->dirty) return IFGP_OK;
     const int d = t->d, Dp = padded_dim(d), S = Dp / 4;
-    const int64_t M = t->clusters, nblk = ceil_div(M, (int64_t)16), Mp = nblk * 16;
+    // two spare blocks (zero centroids of norm +inf) after the last: the
+    // kernel loads a block or two ahead without bounds checks
+    const int64_t M = t->clusters, Mp = (ceil_div(M, (int64_t)16) + LABEL_SPARE) * 16;
     std::vector<double> h((size_t)Mp * Dp + (size_t)Mp, 0.0);
     double *frag = h.data(), *nrm = h.data() + (size_t)Mp * Dp;
     for (int64_t m = M; m < Mp; ++m) nrm[m] = INFINITY;
@@ -593,7 +606,7 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
     }
     const int64_t nblk = ceil_div(b->clusters, (int64_t)16);
     const double *F = b->centers.as<double>();
-    const double *cn = F + nblk * 16 * b->Dp;
+    const double *cn = F + (nblk + LABEL_SPARE) * 16 * b->Dp;
 #define IFGP_LABEL(DP, RB)                                                                  \
     birch_label_kernel<DP, RB><<<(unsigned)ceil_div(n, (int64_t)16 * RB * LW), 64 * LW, 0, s>>>( \
         Z, n, b->d, F, cn, nblk, labels)
