@@ -169,3 +169,21 @@ def test_jobs_admitted_between_hops(ifgp):
     assert e.value.status == -5
     for G in graphs:
         G.destroy()
+
+
+def test_batch_equals_alone_large(ifgp):
+    """Graphs whose BF16 features exceed 128 MB gather fewer rows at a time;
+    the choice belongs to the graph, so a large graph batched with small ones
+    and two large ones batched together give what each gives alone."""
+    import torch
+    big = dcsbm(1_100_000, 120, mean_deg=12.0, ratio=2.5, seed=5)   # 1.1M x 64 BF16 = 141 MB
+    big2 = dcsbm(1_050_000, 110, mean_deg=10.0, ratio=3.0, seed=6)
+    small = dcsbm(30_000, 30, mean_deg=20.0, ratio=2.5, seed=7)
+    gs = [ifgp.Graph(g.src, g.dst, g.N) for g in (big, small, big2)]
+    outs = ifgp.embed_batch(gs, [-1.0, -1.0, -1.5], [4, 4, 3], [64, 64, 64], [1, 2, 3],
+                            storage="bf16")
+    for G, o, t, K, sd in zip(gs, outs, [-1.0, -1.0, -1.5], [4, 4, 3], [1, 2, 3]):
+        alone = G.embed(t, K, 64, sd, storage="bf16")
+        assert torch.equal(o, alone)
+    for G in gs:
+        G.destroy()
