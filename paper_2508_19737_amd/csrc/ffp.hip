@@ -39,25 +39,31 @@ constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / 64;
 // Neighbour rows in flight per lane: 16-byte loads of 4-byte storage cover
 // half as many columns as those of 2-byte storage, so they get twice the
-// depth.  With SH (shallow), chosen per graph when its 2-byte feature rows
-// span 64 columns or more and the feature matrix is larger than half the
-// Infinity Cache, 2-byte rows get fewer (measured on the 2M-node graph at
-// width 64: 4 rows 0.777 ms against 8 rows 0.788 ms per hop; on a 200k-node
-// graph, whose features stay in cache, 4 rows lose 20%).
+// depth.  For 2-byte storage the depth is chosen per graph (hop_depth): a
+// feature matrix that stays in cache gathers more rows at a time, one far
+// beyond the Infinity Cache with rows of 64 columns or more fewer (measured
+// per hop at width 64: 200k nodes 91 us with 8 rows, 83 us with 16; 1M nodes
+// 387 us with 8, 397 with 16, 425 with 4; 2M nodes 0.788 ms with 8, 0.777 ms
+// with 4).
 #ifndef IFGP_HOP_UNROLL_2B
 #define IFGP_HOP_UNROLL_2B 8
 #endif
-#ifndef IFGP_HOP_UNROLL_2B_WIDE
-#define IFGP_HOP_UNROLL_2B_WIDE 4
+#ifndef IFGP_HOP_UNROLL_2B_SHALLOW
+#define IFGP_HOP_UNROLL_2B_SHALLOW 4
 #endif
+#ifndef IFGP_HOP_UNROLL_2B_DEEP
+#define IFGP_HOP_UNROLL_2B_DEEP 16
+#endif
+enum HopDepth { DEPTH_NORMAL = 0, DEPTH_SHALLOW = 1, DEPTH_DEEP = 2 };
 #ifndef IFGP_HOP_UNROLL_4B
 #define IFGP_HOP_UNROLL_4B 16
 #endif
 
-template <typename T, int D, bool SH = false> struct Cfg {
-    static constexpr int U = sizeof(T) == 4  ? IFGP_HOP_UNROLL_4B
-                             : (SH && D >= 64) ? IFGP_HOP_UNROLL_2B_WIDE
-                                               : IFGP_HOP_UNROLL_2B;
+template <typename T, int D, int DEPTH = DEPTH_NORMAL> struct Cfg {
+    static constexpr int U = sizeof(T) == 4                         ? IFGP_HOP_UNROLL_4B
+                             : (DEPTH == DEPTH_SHALLOW && D >= 64) ? IFGP_HOP_UNROLL_2B_SHALLOW
+                             : DEPTH == DEPTH_DEEP                 ? IFGP_HOP_UNROLL_2B_DEEP
+                                                                   : IFGP_HOP_UNROLL_2B;
     static constexpr int EPL = 16 / (int)sizeof(T);   // elements per lane
     static constexpr int LPR = D / EPL;               // lanes per row
     static constexpr int RPW = 64 / LPR;              // rows (subgroups) per wave
@@ -381,12 +387,12 @@ struct HopArgs {
 
 // Gather-add W rows of neighbours e in [first, end) visited in chunks of U
 // starting every `step`: acc[e] += sum W[j, sl*EPL + e].
-template <typename T, int D, bool SH>
+template <typename T, int D, int DEPTH>
 __device__ __forceinline__ void gather_add(const int32_t *__restrict__ colidx,
                                            const char *__restrict__ Win, int64_t first,
                                            int64_t end, int64_t step, int sl, int lane_base,
                                            float *acc) {
-    using C = Cfg<T, D, SH>;
+    using C = Cfg<T, D, DEPTH>;
     constexpr int EPL = C::EPL, LPR = C::LPR, QI = C::QI, U = C::U;
     const int64_t col_off = (int64_t)sl * EPL * (int64_t)sizeof(T);
     for (int64_t e0 = first; e0 < end; e0 += step) {
@@ -446,9 +452,9 @@ __device__ __forceinline__ void row_finish(const HopArgs &a, int64_t r, int sl, 
     }
 }
 
-template <typename T, int D, bool SH>
+template <typename T, int D, int DEPTH>
 __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
-    using C = Cfg<T, D, SH>;
+    using C = Cfg<T, D, DEPTH>;
     constexpr int EPL = C::EPL, LPR = C::LPR, RPW = C::RPW, U = C::U;
     __shared__ float lds_acc[WAVES][D];
     __shared__ double2 lds_st[WAVES][D];
@@ -473,7 +479,7 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
         const int64_t beg = a.rowptr[r], end = a.rowptr[r + 1];
-        gather_add<T, D, SH>(a.colidx, Win, beg + (int64_t)(w * RPW + g) * U, end,
+        gather_add<T, D, DEPTH>(a.colidx, Win, beg + (int64_t)(w * RPW + g) * U, end,
                          (int64_t)WAVES * RPW * U, sl, lane_base, acc);
 #pragma unroll
         for (int off = LPR; off < 64; off <<= 1)
@@ -499,7 +505,7 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
 #pragma unroll
             for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
             const int64_t beg = a.rowptr[r], end = a.rowptr[r + 1];
-            gather_add<T, D, SH>(a.colidx, Win, beg + (int64_t)g * U, end, (int64_t)RPW * U, sl,
+            gather_add<T, D, DEPTH>(a.colidx, Win, beg + (int64_t)g * U, end, (int64_t)RPW * U, sl,
                              lane_base, acc);
 #pragma unroll
             for (int off = LPR; off < 64; off <<= 1)
@@ -517,7 +523,7 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
                 float acc[EPL];
 #pragma unroll
                 for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
-                gather_add<T, D, SH>(a.colidx, Win, a.rowptr[r], a.rowptr[r + 1], (int64_t)U, sl,
+                gather_add<T, D, DEPTH>(a.colidx, Win, a.rowptr[r], a.rowptr[r + 1], (int64_t)U, sl,
                                  lane_base, acc);
                 row_finish<T, D>(a, r, sl, acc, av, bv, ssum, ssq);
             }
@@ -547,9 +553,9 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
     }
 }
 
-template <typename T, int D, bool SH>
+template <typename T, int D, int DEPTH>
 __global__ __launch_bounds__(THREADS) void hop_kernel(const HopArgs a) {
-    hop_block<T, D, SH>(a, blockIdx.x);
+    hop_block<T, D, DEPTH>(a, blockIdx.x);
 }
 
 // Many graphs in one launch; the table travels as a kernel argument (no
@@ -563,12 +569,12 @@ struct HopBatch {
 };
 static_assert(sizeof(HopBatch) <= 3584, "batch table must fit the kernel argument segment");
 
-template <typename T, int D, bool SH>
+template <typename T, int D, int DEPTH>
 __global__ __launch_bounds__(THREADS) void hop_batch_kernel(const HopBatch bt) {
     const int64_t b = blockIdx.x;
     int gi = 0;
     while (gi + 1 < bt.n && bt.start[gi + 1] <= b) ++gi;
-    hop_block<T, D, SH>(bt.a[gi], b - bt.start[gi]);
+    hop_block<T, D, DEPTH>(bt.a[gi], b - bt.start[gi]);
 }
 
 // mu, sigma per column from the block partials (fixed order), then
@@ -762,39 +768,59 @@ FinArgs make_fin_args(ifgp_graph_s *h) {
     return f;
 }
 
-// Fewer neighbour rows in flight (see Cfg) for 2-byte rows of width >= 64
-// whose feature matrix exceeds 128 MB (half the Infinity Cache).
-constexpr int64_t SHALLOW_MIN_BYTES = (int64_t)128 << 20;
-bool hop_shallow(const GraphData &g, int Dp, int storage) {
-    return dtype_bytes(storage) == 2 && Dp >= 64 && g.N * (int64_t)Dp * 2 >= SHALLOW_MIN_BYTES;
+// The gather depth of a graph's hops (see Cfg): 2-byte feature matrices of
+// at most 32 MiB gather deep, those of 224 MiB or more with rows of 64
+// columns or more shallow.  It depends on the graph only, so a graph's
+// result is the same alone and in any batch.
+constexpr int64_t DEEP_MAX_BYTES = (int64_t)32 << 20;
+constexpr int64_t SHALLOW_MIN_BYTES = (int64_t)224 << 20;
+int hop_depth(const GraphData &g, int Dp, int storage) {
+    if (dtype_bytes(storage) != 2) return DEPTH_NORMAL;
+    const int64_t bytes = g.N * (int64_t)Dp * 2;
+    if (Dp >= 64 && bytes >= SHALLOW_MIN_BYTES) return DEPTH_SHALLOW;
+    if (bytes <= DEEP_MAX_BYTES) return DEPTH_DEEP;
+    return DEPTH_NORMAL;
 }
 
-// The shallow variant exists only where it differs (2-byte rows, width >= 64).
+// Variants other than the normal depth exist only for 2-byte storage (and
+// the shallow one for widths >= 64), where they differ.
 template <typename T, int D>
-ifgp_status hop_launch(const HopArgs &a, bool shallow, hipStream_t s) {
-    if constexpr (sizeof(T) == 2 && D >= 64)
-        if (shallow) {
-            hop_kernel<T, D, true><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+ifgp_status hop_launch(const HopArgs &a, int depth, hipStream_t s) {
+    if constexpr (sizeof(T) == 2) {
+        if constexpr (D >= 64)
+            if (depth == DEPTH_SHALLOW) {
+                hop_kernel<T, D, DEPTH_SHALLOW><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+                return IFGP_OK;
+            }
+        if (depth == DEPTH_DEEP) {
+            hop_kernel<T, D, DEPTH_DEEP><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
             return IFGP_OK;
         }
-    hop_kernel<T, D, false><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+    }
+    hop_kernel<T, D, DEPTH_NORMAL><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
     return IFGP_OK;
 }
 
 template <typename T, int D>
-ifgp_status hop_batch_launch(const HopBatch &bt, int64_t total_blocks, bool shallow,
+ifgp_status hop_batch_launch(const HopBatch &bt, int64_t total_blocks, int depth,
                              hipStream_t s) {
-    if constexpr (sizeof(T) == 2 && D >= 64)
-        if (shallow) {
-            hop_batch_kernel<T, D, true><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+    if constexpr (sizeof(T) == 2) {
+        if constexpr (D >= 64)
+            if (depth == DEPTH_SHALLOW) {
+                hop_batch_kernel<T, D, DEPTH_SHALLOW><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+                return IFGP_OK;
+            }
+        if (depth == DEPTH_DEEP) {
+            hop_batch_kernel<T, D, DEPTH_DEEP><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
             return IFGP_OK;
         }
-    hop_batch_kernel<T, D, false><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+    }
+    hop_batch_kernel<T, D, DEPTH_NORMAL><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
     return IFGP_OK;
 }
 
-ifgp_status launch_hop(const HopArgs &a, int storage, int Dp, bool shallow, hipStream_t s) {
-#define HOP_CALL(T, D) hop_launch<T, D>(a, shallow, s)
+ifgp_status launch_hop(const HopArgs &a, int storage, int Dp, int depth, hipStream_t s) {
+#define HOP_CALL(T, D) hop_launch<T, D>(a, depth, s)
     IFGP_DISPATCH(storage, Dp, HOP_CALL);
 #undef HOP_CALL
     set_error("unsupported storage/width");
@@ -802,8 +828,8 @@ ifgp_status launch_hop(const HopArgs &a, int storage, int Dp, bool shallow, hipS
 }
 
 ifgp_status launch_hop_batch(const HopBatch &bt, int64_t total_blocks, int storage, int Dp,
-                             bool shallow, hipStream_t s) {
-#define HOPB_CALL(T, D) hop_batch_launch<T, D>(bt, total_blocks, shallow, s)
+                             int depth, hipStream_t s) {
+#define HOPB_CALL(T, D) hop_batch_launch<T, D>(bt, total_blocks, depth, s)
     IFGP_DISPATCH(storage, Dp, HOPB_CALL);
 #undef HOPB_CALL
     set_error("unsupported storage/width");
@@ -1053,20 +1079,19 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
     // and one finalize launch per group.  A graph's gather depth depends on
     // the graph only, so its result is the same alone and in any batch.
     struct Group {
-        int storage, Dp;
-        bool shallow;
+        int storage, Dp, depth;
         std::vector<ifgp_graph_s *> members;
     };
     std::vector<Group> groups;
     for (int i = 0; i < n; ++i) {
         ifgp_graph_s *h = hs[i];
         if (!h->job.active || h->job.done) continue;
-        const bool sh = hop_shallow(h->g, h->job.Dp, h->job.storage);
+        const int dep = hop_depth(h->g, h->job.Dp, h->job.storage);
         Group *gp = nullptr;
         for (auto &G : groups)
-            if (G.storage == h->job.storage && G.Dp == h->job.Dp && G.shallow == sh) gp = &G;
+            if (G.storage == h->job.storage && G.Dp == h->job.Dp && G.depth == dep) gp = &G;
         if (!gp) {
-            groups.push_back({h->job.storage, h->job.Dp, sh, {}});
+            groups.push_back({h->job.storage, h->job.Dp, dep, {}});
             gp = &groups.back();
         }
         gp->members.push_back(h);
@@ -1076,7 +1101,7 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
             ifgp_graph_s *h = G.members[0];
             const HopArgs a = make_hop_args(h);
             IFGP_TRY(record_event(h, s, true));
-            IFGP_TRY(launch_hop(a, G.storage, G.Dp, G.shallow, s));
+            IFGP_TRY(launch_hop(a, G.storage, G.Dp, G.depth, s));
             IFGP_LAUNCHED();
             IFGP_TRY(record_event(h, s, false));
             const FinArgs f = make_fin_args(h);
@@ -1096,7 +1121,7 @@ ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {
                     bt.start[i + 1] = bt.start[i] + bt.a[i].blocks;
                 }
                 for (int i = 0; i < nb; ++i) IFGP_TRY(record_event(G.members[b0 + i], s, true));
-                IFGP_TRY(launch_hop_batch(bt, bt.start[nb], G.storage, G.Dp, G.shallow, s));
+                IFGP_TRY(launch_hop_batch(bt, bt.start[nb], G.storage, G.Dp, G.depth, s));
                 IFGP_LAUNCHED();
                 for (int i = 0; i < nb; ++i) IFGP_TRY(record_event(G.members[b0 + i], s, false));
                 finalize_batch_kernel<<<dim3((unsigned)G.Dp, (unsigned)nb), FIN_THREADS, 0, s>>>(fb);

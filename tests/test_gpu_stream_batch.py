@@ -171,18 +171,18 @@ def test_jobs_admitted_between_hops(ifgp):
         G.destroy()
 
 
-def test_batch_equals_alone_large(ifgp):
-    """Graphs whose BF16 features exceed 128 MB gather fewer rows at a time;
-    the choice belongs to the graph, so a large graph batched with small ones
-    and two large ones batched together give what each gives alone."""
+def test_batch_equals_alone_depths(ifgp):
+    """A graph's gather depth follows from its size (BF16 features of at most
+    32 MiB gather deep, 224 MiB or more shallow, others the normal depth), so
+    a batch holding all three kinds gives what each graph gives alone."""
     import torch
-    big = dcsbm(1_100_000, 120, mean_deg=12.0, ratio=2.5, seed=5)   # 1.1M x 64 BF16 = 141 MB
-    big2 = dcsbm(1_050_000, 110, mean_deg=10.0, ratio=3.0, seed=6)
-    small = dcsbm(30_000, 30, mean_deg=20.0, ratio=2.5, seed=7)
-    gs = [ifgp.Graph(g.src, g.dst, g.N) for g in (big, small, big2)]
-    outs = ifgp.embed_batch(gs, [-1.0, -1.0, -1.5], [4, 4, 3], [64, 64, 64], [1, 2, 3],
-                            storage="bf16")
-    for G, o, t, K, sd in zip(gs, outs, [-1.0, -1.0, -1.5], [4, 4, 3], [1, 2, 3]):
+    big = dcsbm(1_900_000, 150, mean_deg=8.0, ratio=2.5, seed=5)     # 243 MB of features
+    mid = dcsbm(400_000, 80, mean_deg=12.0, ratio=3.0, seed=6)       # 51 MB
+    small = dcsbm(30_000, 30, mean_deg=20.0, ratio=2.5, seed=7)      # 4 MB
+    gs = [ifgp.Graph(g.src, g.dst, g.N) for g in (big, small, mid)]
+    taus, Ks, seeds = [-1.0, -1.0, -1.5], [3, 4, 3], [1, 2, 3]
+    outs = ifgp.embed_batch(gs, taus, Ks, [64, 64, 64], seeds, storage="bf16")
+    for G, o, t, K, sd in zip(gs, outs, taus, Ks, seeds):
         alone = G.embed(t, K, 64, sd, storage="bf16")
         assert torch.equal(o, alone)
     for G in gs:
