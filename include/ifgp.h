@@ -167,7 +167,9 @@ IFGP_API ifgp_status ifgp_stream_add(ifgp_graph_t g, const int64_t *src, const i
 
 /*
  * Embed several graphs together: every hop of every graph runs in one
- * launch per (storage, padded width) class, so small graphs share the device.
+ * launch per (storage, padded width, gather depth) class, so small graphs
+ * share the device (the gather depth, the neighbour rows a lane keeps in
+ * flight, follows from the graph's feature-matrix size alone).
  * Arrays have n entries; outs[k] is graph k's device N_k x d_k FP32 output.
  * The result for each graph is identical to ifgp_embed on that graph alone.
  * A handle may appear at most once.  Errors as ifgp_embed.

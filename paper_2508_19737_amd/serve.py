@@ -12,7 +12,7 @@ Algorithm 2) generalised to a stream of independent graphs.  The loop
     construction overlaps the hops of graphs already running;
   * starts a graph's job at the next hop boundary once its build is done;
   * advances every running job by one hop per iteration, all graphs of one
-    (storage, width) class in one kernel launch (ifgp_job_step);
+    (storage, width, gather depth) class in one kernel launch (ifgp_job_step);
   * retires a job when its output is complete on the device, frees its slot
     and memory, and records its latency (completion - arrival).
 
