@@ -78,21 +78,34 @@ def cpu_info():
     return model
 
 
-def cpu_baseline_parallel(g, rp, ci, tau, K, d, cols):
+def cpu_baseline_parallel(g, rp, ci, tau, K, d, cols, cols_1t=2):
     """The plain-C FP64 oracle (OpenMP over rows) on a column sample of the
-    same workload, on every host core it is given (OMP_NUM_THREADS)."""
+    same workload, on every host core it is given (OMP_NUM_THREADS), and on
+    one thread (a smaller sample)."""
+    import ctypes
     import os
     from oracle import cref
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    nnz = int(rp[-1])
     X = cref.gaussian_input(g.N, cols, 1)
     t0 = time.perf_counter()
     cref.ffp_from_input(rp, ci, g.N, tau, K, X)
     t = time.perf_counter() - t0
-    nnz = int(rp[-1])
+    one = None
+    try:   # the OpenMP runtime the C oracle runs on
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        X1 = np.ascontiguousarray(X[:, :cols_1t])
+        t1 = time.perf_counter()
+        cref.ffp_from_input(rp, ci, g.N, tau, K, X1)
+        one = nnz * cols_1t * K / (time.perf_counter() - t1)
+        gomp.omp_set_num_threads(threads)
+    except OSError:
+        pass
     return {"value": nnz * cols * K / t, "unit": "nnz*d*K/s", "cores": threads,
-            "kind": "oracle (C, OpenMP)",
-            "sample": f"plain-C FP64 oracle ({K} hops, sigmoid) on {cols} columns of the same graph; "
-                      f"{t:.1f} s"}
+            "kind": "oracle (C, OpenMP)", "value_1_thread": one,
+            "sample": f"plain-C FP64 oracle ({K} hops, sigmoid) on {cols} columns of the same graph "
+                      f"({t:.1f} s), and on {cols_1t} columns with one thread"}
 
 
 def cpu_baseline(g, rp, ci, tau, K, d, cols):
