@@ -79,3 +79,37 @@ def test_call_orders_after_a_build(big):
     c = G.embed(-1.0, 8, 64, 1, storage="bf16").cpu()
     G.destroy()
     assert torch.equal(c, a)
+
+
+def test_streaming_full_size():
+    """The streaming workload at the size bench.py times: DC-SBM N = 200,000
+    (100 blocks, mean degree 20), edges shuffled (seed 2) into 10 increments
+    merged one by one with re-embedding (d = 64, tau = -1, K = 8, BF16).
+    After every increment the CSR is bit-exact against the canonical CSR of
+    all edges so far; the last embedding equals a fresh build's bit for bit
+    and matches the oracle on sampled columns."""
+    import torch
+    import paper_2508_19737_amd as ifgp
+    from workloads import shuffled_increments
+    g = dcsbm(200_000, 100, mean_deg=20.0, ratio=2.5, seed=0)
+    incs = shuffled_increments(g, 10, seed=2)
+    G = ifgp.Graph(np.zeros(0, np.int64), np.zeros(0, np.int64), g.N)
+    src = np.zeros(0, np.int64)
+    dst = np.zeros(0, np.int64)
+    for s, t in incs:
+        G.stream_add(torch.as_tensor(s, device="cuda"), torch.as_tensor(t, device="cuda"))
+        src, dst = np.concatenate([src, s]), np.concatenate([dst, t])
+        rp, ci, _, _ = ffp.canonical_csr(src, dst, g.N)
+        grp, gci, _ = G.export_csr()
+        assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
+    got = G.embed(-1.0, 8, 64, 1, storage="bf16").cpu().numpy()
+    G.destroy()
+    F = ifgp.Graph(src, dst, g.N)
+    fresh = F.embed(-1.0, 8, 64, 1, storage="bf16").cpu().numpy()
+    F.destroy()
+    assert np.array_equal(got, fresh)
+    X = ffp.gaussian_input(g.N, 64, seed=1, cols=COLS)
+    ref = cref.ffp_from_input(rp, ci, g.N, -1.0, 8, X)
+    err = ffp.rel_frobenius(got[:, COLS], ref)
+    print(f"streaming 200k nodes bf16: rel_frobenius on columns {COLS} = {err:.3e}", flush=True)
+    assert err <= 1e-2
