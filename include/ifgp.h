@@ -244,6 +244,18 @@ IFGP_API ifgp_status ifgp_empty_cache(void);
 IFGP_API ifgp_status ifgp_timing_enable(ifgp_graph_t g, int enable);
 IFGP_API ifgp_status ifgp_timing_read(ifgp_graph_t g, int64_t *hop_launches, double *hop_ms);
 
+/*
+ * Test hook for the grids of the kernels that can pass a launch's 2^32
+ * work items per dimension (one thread per matrix entry, one block per few
+ * rows, on graphs of several hundred million nodes): such grids put at most
+ * max_x_blocks blocks in x and continue in y.  Lowering it lets small inputs
+ * take the two-dimensional path.  max_x_blocks = 0 restores the default
+ * (2^21); negative values are rejected (IFGP_E_INVALID).  *previous (may be
+ * NULL) receives the value in force before the call.  Process-wide; results
+ * do not depend on it.  Not for use while other threads launch work.
+ */
+IFGP_API ifgp_status ifgp_debug_grid_x(int64_t max_x_blocks, int64_t *previous);
+
 /* Release the handle and all its device memory (NULL is accepted). */
 IFGP_API ifgp_status ifgp_destroy(ifgp_graph_t g);
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "ifgp_job_step", "ifgp_graph_info", "ifgp_plan_info", "ifgp_export_csr",
     "ifgp_export_scales",
     "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_empty_cache", "ifgp_timing_enable",
-    "ifgp_timing_read",
+    "ifgp_timing_read", "ifgp_debug_grid_x",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
     "ifgp_birch_create", "ifgp_birch_partial_fit", "ifgp_birch_info", "ifgp_birch_centers",
     "ifgp_birch_predict", "ifgp_birch_destroy",
@@ -75,6 +75,7 @@ def _load():
         "ifgp_empty_cache": [],
         "ifgp_timing_enable": [P, ctypes.c_int],
         "ifgp_timing_read": [P, P, P],
+        "ifgp_debug_grid_x": [i64, P],
         "ifgp_destroy": [P],
         "ifgp_birch_create": [i32, f64, i32, ctypes.POINTER(P)],
         "ifgp_birch_partial_fit": [P, P, i64, ctypes.c_int, P],
@@ -172,6 +173,14 @@ def use_hip_allocator():
 def empty_cache():
     """Return the library allocator's cached blocks to the device."""
     check(lib.ifgp_empty_cache())
+
+
+def debug_grid_x(max_x_blocks: int) -> int:
+    """Test hook: cap the x dimension of the size-dependent grids at
+    max_x_blocks blocks (0 = the default); returns the previous cap."""
+    prev = ctypes.c_int64()
+    check(lib.ifgp_debug_grid_x(int(max_x_blocks), ctypes.byref(prev)))
+    return prev.value
 
 
 def _edges(src, dst):

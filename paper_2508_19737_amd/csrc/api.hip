@@ -3,6 +3,7 @@
 // strings and hop timing.  Every device step is a kernel in graph.hip,
 // primitives.hip or ffp.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -107,6 +108,12 @@ size_t size_class(size_t n) {
 }  // namespace
 
 void release_cached_blocks() { cache().release_all(); }
+
+namespace {
+std::atomic<int64_t> g_grid_x{GRID_X_BLOCKS};
+}  // namespace
+
+int64_t grid_x_blocks() { return g_grid_x.load(std::memory_order_relaxed); }
 
 void *raw_alloc(size_t bytes, hipStream_t s, FreeFn *free_fn, void **ctx) {
     if (g_hook.alloc) {
@@ -482,6 +489,16 @@ IFGP_API ifgp_status ifgp_set_allocator(void *(*alloc_fn)(size_t, void *, void *
 
 IFGP_API ifgp_status ifgp_empty_cache(void) {
     release_cached_blocks();
+    return IFGP_OK;
+}
+
+IFGP_API ifgp_status ifgp_debug_grid_x(int64_t max_x_blocks, int64_t *previous) {
+    if (max_x_blocks < 0) {
+        set_error("ifgp_debug_grid_x: max_x_blocks must be >= 0");
+        return IFGP_E_INVALID;
+    }
+    const int64_t prev = g_grid_x.exchange(max_x_blocks ? max_x_blocks : GRID_X_BLOCKS);
+    if (previous) *previous = prev;
     return IFGP_OK;
 }
 

@@ -353,8 +353,8 @@ __global__ __launch_bounds__(64 * LW) void birch_label_kernel(const float *__res
                                                               int32_t *__restrict__ labels) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
-    const int64_t p0 = ((int64_t)blockIdx.x * LW + (threadIdx.x >> 6)) * (16 * RB);
-    if (p0 >= n) return;  // the whole wave
+    const int64_t p0 = (block_index() * LW + (threadIdx.x >> 6)) * (16 * RB);
+    if (p0 >= n) return;  // the whole wave (and every block past the last)
     double a[RB][S];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -608,7 +608,7 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
     const double *F = b->centers.as<double>();
     const double *cn = F + (nblk + LABEL_SPARE) * 16 * b->Dp;
 #define IFGP_LABEL(DP, RB)                                                                  \
-    birch_label_kernel<DP, RB><<<(unsigned)ceil_div(n, (int64_t)16 * RB * LW), 64 * LW, 0, s>>>( \
+    birch_label_kernel<DP, RB><<<grid_for(ceil_div(n, (int64_t)16 * RB * LW)), 64 * LW, 0, s>>>( \
         Z, n, b->d, F, cn, nblk, labels)
     switch (b->Dp) {
     // one row block per wave: more waves in flight beat more independent

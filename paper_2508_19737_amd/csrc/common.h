@@ -89,6 +89,28 @@ ifgp_status ensure(Buf &b, size_t bytes, hipStream_t s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---------------------------------------------------------------- grids
+// A launch holds at most 2^32 - 1 work items per grid dimension, which a
+// kernel with one thread per entry of an N x d matrix, or one block per few
+// rows, passes on graphs that still fit in device memory.  Such kernels take
+// their grid from grid_for: at most grid_x_blocks() blocks in x (2^21, so
+// that blocks of up to 1024 threads stay below 2^31 work items), the rest in
+// y, and x widened so that y stays below 65536.  The kernel reads its linear
+// block index from block_index(); the blocks past the requested count (at the
+// end of the last y row) must leave at once.
+constexpr int64_t GRID_X_BLOCKS = int64_t(1) << 21;
+int64_t grid_x_blocks();  // GRID_X_BLOCKS unless lowered by ifgp_debug_grid_x
+inline dim3 grid_for(int64_t blocks) {
+    int64_t x = grid_x_blocks();
+    if (blocks <= x) return dim3((unsigned)blocks);
+    const int64_t xmin = ceil_div(blocks, 65535);
+    if (x < xmin) x = xmin;
+    return dim3((unsigned)x, (unsigned)ceil_div(blocks, x));
+}
+__device__ __forceinline__ int64_t block_index() {
+    return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+}
+
 // ---------------------------------------------------------------- storage types
 struct bf16_t {
     uint16_t x;

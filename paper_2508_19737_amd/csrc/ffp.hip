@@ -222,7 +222,7 @@ __device__ __forceinline__ void gaussian4_f32(uint64_t seed, int64_t i, int64_t 
 template <typename T>
 __global__ void gaussian_kernel(int64_t N, int d, uint64_t seed, T *out) {
     const int64_t nq = (d + 3) / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = block_index() * blockDim.x + threadIdx.x;
     if (t >= N * nq) return;
     const int64_t i = t / nq, q = t - i * nq;
     double z[4];
@@ -243,7 +243,7 @@ template <typename T, int D>
 __global__ void noise_kernel(int64_t N, int d, uint64_t seed, const int32_t *__restrict__ perm,
                              const double *__restrict__ s64, T *__restrict__ W) {
     constexpr int NQ = D / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = block_index() * blockDim.x + threadIdx.x;
     if (t >= N * NQ) return;
     const int64_t k = t / NQ;
     const int q = (int)(t % NQ);
@@ -273,7 +273,7 @@ template <typename T, int D>
 __global__ void prep_x_kernel(int64_t N, int d, const float *__restrict__ X,
                               const int32_t *__restrict__ perm, const double *__restrict__ s64,
                               T *__restrict__ W) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = block_index() * blockDim.x + threadIdx.x;
     if (t >= N * D) return;
     const int64_t k = t / D;
     const int c = (int)(t % D);
@@ -299,7 +299,7 @@ __device__ __forceinline__ double dtau_of(double deg, double tau, double eps) {
 
 __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, double tau,
                               double eps, double *__restrict__ s64, float *__restrict__ s32) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = block_index() * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
     const double sk = 1.0 / sqrt(dt);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N, int64_t n_
     int64_t k;
     int l;
     double r;
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = block_index();  // past the last block: k >= N below
     if (blk < heavy_blocks) {
         k = blk * (THREADS / 64) + threadIdx.x / 64;
         l = threadIdx.x % 64;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N, int64_t n_
 
 __global__ void perm_scales_kernel(int64_t N, const int32_t *__restrict__ perm,
                                    const double *__restrict__ s64, double *__restrict__ out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = block_index() * blockDim.x + threadIdx.x;
     if (k < N) out[perm[k]] = s64[k];
 }
 
@@ -555,7 +555,9 @@ __device__ __forceinline__ void hop_block(const HopArgs &a, int64_t blk) {
 
 template <typename T, int D, int DEPTH>
 __global__ __launch_bounds__(THREADS) void hop_kernel(const HopArgs a) {
-    hop_block<T, D, DEPTH>(a, blockIdx.x);
+    const int64_t blk = block_index();
+    if (blk >= a.blocks) return;
+    hop_block<T, D, DEPTH>(a, blk);
 }
 
 // Many graphs in one launch; the table travels as a kernel argument (no
@@ -571,7 +573,8 @@ static_assert(sizeof(HopBatch) <= 3584, "batch table must fit the kernel argumen
 
 template <typename T, int D, int DEPTH>
 __global__ __launch_bounds__(THREADS) void hop_batch_kernel(const HopBatch bt) {
-    const int64_t b = blockIdx.x;
+    const int64_t b = block_index();
+    if (b >= bt.start[bt.n]) return;
     int gi = 0;
     while (gi + 1 < bt.n && bt.start[gi + 1] <= b) ++gi;
     hop_block<T, D, DEPTH>(bt.a[gi], b - bt.start[gi]);
@@ -685,7 +688,7 @@ __global__ __launch_bounds__(THREADS) void epilogue_kernel(int64_t N, int d,
                                                            const int32_t *__restrict__ perm,
                                                            float *__restrict__ out) {
     constexpr int NQ = D / 4;
-    const int64_t gl = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    const int64_t gl = block_index() * THREADS + threadIdx.x;
     const int64_t k = gl / NQ;
     const int c0 = (int)(gl % NQ) * 4;
     if (k >= N || c0 >= d) return;
@@ -789,15 +792,15 @@ ifgp_status hop_launch(const HopArgs &a, int depth, hipStream_t s) {
     if constexpr (sizeof(T) == 2) {
         if constexpr (D >= 64)
             if (depth == DEPTH_SHALLOW) {
-                hop_kernel<T, D, DEPTH_SHALLOW><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+                hop_kernel<T, D, DEPTH_SHALLOW><<<grid_for(a.blocks), THREADS, 0, s>>>(a);
                 return IFGP_OK;
             }
         if (depth == DEPTH_DEEP) {
-            hop_kernel<T, D, DEPTH_DEEP><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+            hop_kernel<T, D, DEPTH_DEEP><<<grid_for(a.blocks), THREADS, 0, s>>>(a);
             return IFGP_OK;
         }
     }
-    hop_kernel<T, D, DEPTH_NORMAL><<<(unsigned)a.blocks, THREADS, 0, s>>>(a);
+    hop_kernel<T, D, DEPTH_NORMAL><<<grid_for(a.blocks), THREADS, 0, s>>>(a);
     return IFGP_OK;
 }
 
@@ -807,15 +810,15 @@ ifgp_status hop_batch_launch(const HopBatch &bt, int64_t total_blocks, int depth
     if constexpr (sizeof(T) == 2) {
         if constexpr (D >= 64)
             if (depth == DEPTH_SHALLOW) {
-                hop_batch_kernel<T, D, DEPTH_SHALLOW><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+                hop_batch_kernel<T, D, DEPTH_SHALLOW><<<grid_for(total_blocks), THREADS, 0, s>>>(bt);
                 return IFGP_OK;
             }
         if (depth == DEPTH_DEEP) {
-            hop_batch_kernel<T, D, DEPTH_DEEP><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+            hop_batch_kernel<T, D, DEPTH_DEEP><<<grid_for(total_blocks), THREADS, 0, s>>>(bt);
             return IFGP_OK;
         }
     }
-    hop_batch_kernel<T, D, DEPTH_NORMAL><<<(unsigned)total_blocks, THREADS, 0, s>>>(bt);
+    hop_batch_kernel<T, D, DEPTH_NORMAL><<<grid_for(total_blocks), THREADS, 0, s>>>(bt);
     return IFGP_OK;
 }
 
@@ -839,8 +842,8 @@ ifgp_status launch_hop_batch(const HopBatch &bt, int64_t total_blocks, int stora
 ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStream_t s) {
     const Job &j = h->job;
     const int64_t n = h->g.N * j.Dp;
-    const unsigned grid = (unsigned)ceil_div(n, THREADS);
-    const unsigned grid4 = (unsigned)ceil_div(n / 4, THREADS);
+    const dim3 grid = grid_for(ceil_div(n, THREADS));
+    const dim3 grid4 = grid_for(ceil_div(n / 4, THREADS));
     void *W = h->ws.feat[0].p;
     const int32_t *perm = h->g.perm.as<int32_t>();
     const double *s64 = h->sc.s64.as<double>();
@@ -865,7 +868,7 @@ ifgp_status launch_epilogue(ifgp_graph_s *h, hipStream_t s) {
     float *out = j.out;
     const int d = j.d;
 #define EPI_CALL(T, D)                                                                          \
-    (epilogue_kernel<T, D><<<(unsigned)ceil_div(N * (D / 4), THREADS), THREADS, 0, s>>>(        \
+    (epilogue_kernel<T, D><<<grid_for(ceil_div(N * (D / 4), THREADS)), THREADS, 0, s>>>(        \
          N, d, W, node, ab, perm, out),                                                         \
      IFGP_OK)
     IFGP_DISPATCH(j.storage, j.Dp, EPI_CALL);
@@ -921,7 +924,7 @@ ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t d
                                   hipStream_t s) {
     const int64_t n = N * ((d + 3) / 4);
     if (n == 0) return IFGP_OK;
-    const unsigned grid = (unsigned)ceil_div(n, THREADS);
+    const dim3 grid = grid_for(ceil_div(n, THREADS));
     switch (dtype) {
     case IFGP_F64: gaussian_kernel<double><<<grid, THREADS, 0, s>>>(N, d, seed, (double *)out); break;
     case IFGP_F32: gaussian_kernel<float><<<grid, THREADS, 0, s>>>(N, d, seed, (float *)out); break;
@@ -942,7 +945,7 @@ ifgp_status launch_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s
     IFGP_TRY(ensure(sc.s64, sizeof(double) * g.N, s));
     IFGP_TRY(ensure(sc.s32, sizeof(float) * g.N, s));
     IFGP_TRY(ensure(sc.nodeinfo, sizeof(float4) * g.N, s));
-    scales_kernel<<<(unsigned)ceil_div(g.N, THREADS), THREADS, 0, s>>>(
+    scales_kernel<<<grid_for(ceil_div(g.N, THREADS)), THREADS, 0, s>>>(
         g.N, g.irowptr.as<int64_t>(), tau, eps, sc.s64.as<double>(), sc.s32.as<float>());
     IFGP_LAUNCHED();
     return IFGP_OK;
@@ -954,7 +957,7 @@ ifgp_status launch_nodeinfo(ifgp_graph_s *h, double tau, double eps, hipStream_t
     const int64_t n_heavy = g.n_hub + g.n_med;
     const int64_t heavy_blocks = ceil_div(n_heavy, THREADS / 64);
     const int64_t light_blocks = ceil_div(g.N - n_heavy, THREADS / NI_LANES);
-    nodeinfo_kernel<<<(unsigned)(heavy_blocks + light_blocks), THREADS, 0, s>>>(
+    nodeinfo_kernel<<<grid_for(heavy_blocks + light_blocks), THREADS, 0, s>>>(
         g.N, n_heavy, heavy_blocks, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
         sc.s64.as<double>(), sc.s32.as<float>(), tau, eps, sc.nodeinfo.as<float4>());
     IFGP_LAUNCHED();
@@ -1007,7 +1010,7 @@ ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s) {
     const int64_t N = h->g.N;
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(double) * N, s));
-    perm_scales_kernel<<<(unsigned)ceil_div(N, THREADS), THREADS, 0, s>>>(
+    perm_scales_kernel<<<grid_for(ceil_div(N, THREADS)), THREADS, 0, s>>>(
         N, h->g.perm.as<int32_t>(), h->sc.s64.as<double>(), tmp.as<double>());
     IFGP_LAUNCHED();
     IFGP_HIP(hipMemcpyAsync(s_host, tmp.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));

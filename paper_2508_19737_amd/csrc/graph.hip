@@ -111,7 +111,9 @@ __device__ __forceinline__ bool keep_key(const uint64_t *__restrict__ k, int64_t
 __global__ __launch_bounds__(T256) void unique_count_kernel(const uint64_t *__restrict__ k,
                                                             int64_t n, int B, int64_t N,
                                                             int64_t *__restrict__ bcount) {
-    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + threadIdx.x;
+    const int64_t blk = block_index();
+    if (blk * UQ_TILE >= n) return;  // past the last tile
+    const int64_t base = blk * UQ_TILE + threadIdx.x;
     int64_t c = 0;
 #pragma unroll
     for (int q = 0; q < UQ_ITEMS; ++q) {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(T256) void unique_count_kernel(const uint64_t *__re
         if (i < n && keep_key(k, i, B, N)) ++c;
     }
     c = block_sum_i64(c);
-    if (threadIdx.x == 0) bcount[blockIdx.x] = c;
+    if (threadIdx.x == 0) bcount[blk] = c;
 }
 
 __global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__restrict__ k,
@@ -128,7 +130,9 @@ __global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__re
                                                             uint64_t *__restrict__ out) {
     __shared__ int wcount[UQ_ITEMS][T256 / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * UQ_TILE + threadIdx.x;
+    const int64_t blk = block_index();
+    if (blk * UQ_TILE >= n) return;  // past the last tile
+    const int64_t base = blk * UQ_TILE + threadIdx.x;
     const uint64_t lt = __lanemask_lt();
     bool keep[UQ_ITEMS];
     uint64_t key[UQ_ITEMS];
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__re
     }
     __syncthreads();
     // kept keys before (round q, wave w): all earlier rounds, then earlier waves
-    int64_t pos = boff[blockIdx.x];
+    int64_t pos = boff[blk];
 #pragma unroll
     for (int q = 0; q < UQ_ITEMS; ++q) {
         int before = 0, round = 0;
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__re
 // rowptr[r] = first index p with ukeys[p] >= (r << B), r = 0..N
 __global__ void rowptr_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
                               int B, int64_t N, int64_t *__restrict__ rowptr) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = block_index() * blockDim.x + threadIdx.x;
     if (r > N) return;
     const uint64_t target = (uint64_t)r << B;
     int64_t lo = 0, hi = *nnz_d;
@@ -175,7 +179,7 @@ __global__ void rowptr_kernel(const uint64_t *__restrict__ uk, const int64_t *__
 
 __global__ void colidx_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
                               int64_t bound, uint64_t mask, int32_t *__restrict__ colidx) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = block_index() * blockDim.x + threadIdx.x;
     if (p < bound && p < *nnz_d) colidx[p] = (int32_t)(uk[p] & mask);
 }
 
@@ -219,14 +223,14 @@ __global__ __launch_bounds__(T256) void degree_kernel(const int64_t *__restrict_
 // descending degree, ties by id
 __global__ void order_keys_kernel(const int32_t *__restrict__ deg, int64_t N, int32_t top, int B,
                                   uint64_t *__restrict__ keys) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = block_index() * blockDim.x + threadIdx.x;
     if (i < N) keys[i] = ((uint64_t)(top - deg[i]) << B) | (uint64_t)i;
 }
 
 __global__ void perm_kernel(const uint64_t *__restrict__ keys, int64_t N, uint64_t mask,
                             const int32_t *__restrict__ deg, int32_t *__restrict__ perm,
                             int32_t *__restrict__ iperm, int32_t *__restrict__ ideg) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = block_index() * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int32_t node = (int32_t)(keys[k] & mask);
     perm[k] = node;
@@ -243,7 +247,7 @@ __global__ void relabel_kernel(const uint64_t *__restrict__ uk, int64_t nnz, int
                                const int32_t *__restrict__ iperm,
                                const int64_t *__restrict__ irowptr,
                                int32_t *__restrict__ icolidx) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = block_index() * blockDim.x + threadIdx.x;
     if (p >= nnz) return;
     const uint64_t key = uk[p];
     const int64_t i = (int64_t)(key >> B);
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(T256) void csr_keys_kernel(const int64_t *__restric
                                                         const int32_t *__restrict__ colidx,
                                                         int64_t N, int B,
                                                         uint64_t *__restrict__ keys) {
-    const int64_t r = (int64_t)blockIdx.x * (T256 / 16) + (threadIdx.x >> 4);
+    const int64_t r = block_index() * (T256 / 16) + (threadIdx.x >> 4);
     const int l = threadIdx.x & 15;
     if (r >= N) return;
     for (int64_t t = rowptr[r] + l; t < rowptr[r + 1]; t += 16)
@@ -270,7 +274,7 @@ __global__ void merge_rank_kernel(const uint64_t *__restrict__ a, int64_t na,
                                   const uint64_t *__restrict__ b, const int64_t *__restrict__ nb_d,
                                   int64_t nb_bound, uint64_t sentinel,
                                   uint64_t *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = block_index() * blockDim.x + threadIdx.x;
     const int64_t nb = *nb_d;
     if (t < na) {
         const uint64_t x = a[t];
@@ -474,7 +478,7 @@ __device__ __forceinline__ void bucket_survivors(Lds &sh, P src, int64_t n, int 
 // bstart[b] = first key of bucket b (keys sorted by row >> s); bstart[nbk] = n.
 __global__ void bucket_bounds_kernel(const uint64_t *__restrict__ keys, int64_t n, int B, int s,
                                      int64_t nbk, int64_t *__restrict__ bstart) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = block_index() * blockDim.x + threadIdx.x;
     if (b > nbk) return;
     if (b == nbk) {
         bstart[b] = n;
@@ -544,7 +548,7 @@ __device__ __forceinline__ void bucket_degrees(Lds &sh, int64_t b, int s, int64_
 // order: each is handled on its own).  *nbig counts them.
 __global__ void bucket_big_list_kernel(const int64_t *__restrict__ bstart, int64_t nbk,
                                        int64_t *__restrict__ big, int64_t *__restrict__ nbig) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = block_index() * blockDim.x + threadIdx.x;
     if (b < nbk && bstart[b + 1] - bstart[b] > BK_CAP)
         big[atomicAdd((unsigned long long *)nbig, 1ull)] = b;
 }
@@ -555,10 +559,12 @@ __global__ void bucket_big_list_kernel(const int64_t *__restrict__ bstart, int64
 // the degrees of the bucket's rows.
 __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void bucket_csr_kernel(
     const uint64_t *__restrict__ keys, const int64_t *__restrict__ bstart, int64_t N, int B,
-    int s, int32_t *__restrict__ tcol, int32_t *__restrict__ deg, int64_t *__restrict__ stats) {
+    int s, int64_t nbk, int32_t *__restrict__ tcol, int32_t *__restrict__ deg,
+    int64_t *__restrict__ stats) {
     __shared__ BucketLds<BK_THREADS, BK_KPL> sh;
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    const int64_t b = block_index();
+    if (b >= nbk) return;
     const int64_t bs = bstart[b], n64 = bstart[b + 1] - bs;
     if (n64 > BK_CAP) return;
     const int n = (int)n64;
@@ -671,8 +677,8 @@ __global__ __launch_bounds__(FN_THREADS) void bucket_finish_kernel(
     int32_t *__restrict__ icolidx) {
     __shared__ int64_t lo[(1 << BK_SMAX) + 1];
     __shared__ int64_t dst[1 << BK_SMAX];
-    const int64_t b = blockIdx.x, r0 = b << s;
-    if (r0 >= N) return;
+    const int64_t b = block_index(), r0 = b << s;
+    if (r0 >= N) return;  // also every block past the last bucket
     const int nr = (int)((N - r0) < ((int64_t)1 << s) ? (N - r0) : ((int64_t)1 << s));
     const int64_t p0 = rowptr[r0];
     for (int r = threadIdx.x; r <= nr; r += FN_THREADS) lo[r] = rowptr[r0 + r] - p0;
@@ -711,7 +717,7 @@ __global__ __launch_bounds__(FN_THREADS) void bucket_finish_kernel(
     }
 }
 
-inline unsigned grid1(int64_t n, int t = T256) { return (unsigned)ceil_div(n, t); }
+inline dim3 grid1(int64_t n, int t = T256) { return grid_for(ceil_div(n, t)); }
 
 ifgp_status copy_d2h_sync(void *h, const void *d, size_t bytes, hipStream_t s) {
     IFGP_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
@@ -757,12 +763,12 @@ ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStrea
     Buf bc;
     IFGP_TRY(alloc(bc, sizeof(int64_t) * (nb + 1), s));
     if (n > 0) {
-        unique_count_kernel<<<(unsigned)nb, T256, 0, s>>>(k, n, B, N, bc.as<int64_t>());
+        unique_count_kernel<<<grid_for(nb), T256, 0, s>>>(k, n, B, N, bc.as<int64_t>());
         IFGP_LAUNCHED();
     }
     IFGP_TRY(exclusive_scan<int64_t>(bc.as<int64_t>(), bc.as<int64_t>(), nb, nu_d, s));
     if (n > 0) {
-        unique_write_kernel<<<(unsigned)nb, T256, 0, s>>>(k, n, B, N, bc.as<int64_t>(),
+        unique_write_kernel<<<grid_for(nb), T256, 0, s>>>(k, n, B, N, bc.as<int64_t>(),
                                                           uk.as<uint64_t>());
         IFGP_LAUNCHED();
     }
@@ -835,7 +841,7 @@ ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hi
                                                     g.colidx.as<int32_t>());
         IFGP_LAUNCHED();
     }
-    const unsigned dgrid = (unsigned)std::min<int64_t>(grid1(N), 1024);
+    const unsigned dgrid = (unsigned)std::min<int64_t>(ceil_div(N, T256), 1024);
     degree_kernel<<<dgrid, T256, 0, s>>>(g.rowptr.as<int64_t>(), N, g.deg.as<int32_t>(),
                                          ctr + C_MAXDEG);
     IFGP_LAUNCHED();
@@ -916,8 +922,8 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
         g.deg.as<int32_t>(), ctr.as<int64_t>() + C_MAXDEG);
     hipError_t le = hipGetLastError();
     if (le == hipSuccess) {
-        bucket_csr_kernel<<<(unsigned)nbk, BK_THREADS, 0, side ? aux : s>>>(
-            sorted, bst.as<int64_t>(), N, B, sb, tcol.as<int32_t>(), g.deg.as<int32_t>(),
+        bucket_csr_kernel<<<grid_for(nbk), BK_THREADS, 0, side ? aux : s>>>(
+            sorted, bst.as<int64_t>(), N, B, sb, nbk, tcol.as<int32_t>(), g.deg.as<int32_t>(),
             ctr.as<int64_t>() + C_MAXDEG);
         le = hipGetLastError();
     }
@@ -952,7 +958,7 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
     IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * g.nnz, s));
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * g.nnz, s));
     if (g.nnz > 0) {
-        bucket_finish_kernel<<<(unsigned)nbk, FN_THREADS, 0, s>>>(
+        bucket_finish_kernel<<<grid_for(nbk), FN_THREADS, 0, s>>>(
             tcol.as<int32_t>(), bst.as<int64_t>(), g.rowptr.as<int64_t>(), g.iperm.as<int32_t>(),
             g.irowptr.as<int64_t>(), N, sb, g.colidx.as<int32_t>(), g.icolidx.as<int32_t>());
         IFGP_LAUNCHED();

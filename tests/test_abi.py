@@ -66,3 +66,13 @@ def test_footprint_bytes():
         ifgp.footprint_bytes(10, 10, 300, "bf16")
     with pytest.raises(ifgp.IfgpError):
         ifgp.footprint_bytes(10, 10, 3, "f64")
+
+
+def test_debug_grid_x_round_trip():
+    import paper_2508_19737_amd as ifgp
+    lib = ifgp.lib
+    prev = ctypes.c_int64()
+    assert lib.ifgp_debug_grid_x(-1, ctypes.byref(prev)) == -1
+    assert ifgp.debug_grid_x(7) == 2**21       # the default cap
+    assert ifgp.debug_grid_x(0) == 7           # 0 restores the default
+    assert ifgp.debug_grid_x(0) == 2**21
