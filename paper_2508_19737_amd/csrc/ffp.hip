@@ -307,25 +307,68 @@ __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, do
     s32[k] = (float)sk;
 }
 
-// r_k = sum of s over row k's neighbours (FP32 copies of s gathered, summed in
-// FP64).  Rows are in descending-degree order: the first n_heavy rows get one
-// wave each, the rest NI_LANES lanes each; every lane keeps NI_DEPTH
-// independent gathers in flight and the lanes of a row combine by a fixed
-// butterfly (deterministic order).
+// r_k = sum of s over row k's neighbours (FP32 copies of s, summed in FP64).
+// Rows are in descending-degree order: the first n_heavy rows get one wave
+// each, the rest NI_LANES lanes each; every lane keeps NI_DEPTH independent
+// loads in flight and the lanes of a row combine by a fixed butterfly
+// (deterministic order).
+//
+// A neighbour's s comes from a table in LDS where it can.  Internal ids are
+// sorted by degree and s depends on the degree alone, so s is constant over
+// long runs of ids: the table holds, for each bucket of 2^sh consecutive ids,
+// the bucket's s if all its ids have one degree and -1 otherwise (s > 0), and
+// only entries in mixed buckets gather s from memory.  The mixed buckets are
+// those of the few high-degree nodes, whose ids are low and whose s values
+// stay in L2; a random 4-byte gather from the whole N-long table would move
+// a 128-byte line.  The values are the same either way, so the sums are too.
+// Below NI_TABLE_MIN_NODES the whole FP32 s fits in L2 and the table is not
+// built.
 constexpr int NI_LANES = 8;
 constexpr int NI_DEPTH = 4;
+constexpr int NI_TABLE = 4096;      // buckets (16 KB of LDS)
+constexpr int64_t NI_GRID = 2048;   // blocks striding over the row groups
+constexpr int64_t NI_TABLE_MIN_NODES = int64_t(1) << 19;
 
-template <int LANES>
+int ni_shift(int64_t N) {
+    int sh = 0;
+    while (ceil_div(N, (int64_t)1 << sh) > NI_TABLE) ++sh;
+    return sh;
+}
+
+// Bucket k covers internal ids [k 2^sh, min((k+1) 2^sh, N)); degrees are
+// non-increasing in the id, so equal degrees at both ends mean one degree.
+__global__ void s_table_kernel(int64_t N, int sh, int64_t nbk, const int64_t *__restrict__ irowptr,
+                               const float *__restrict__ s32, float *__restrict__ tab) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbk) return;
+    const int64_t lo = k << sh, hi = ((k + 1) << sh < N ? (k + 1) << sh : N) - 1;
+    const int64_t dlo = irowptr[lo + 1] - irowptr[lo], dhi = irowptr[hi + 1] - irowptr[hi];
+    tab[k] = dlo == dhi ? s32[lo] : -1.0f;
+}
+
+template <int LANES, bool TABLE>
 __device__ __forceinline__ double row_neighbour_sum(const int32_t *__restrict__ icolidx,
-                                                    const float *__restrict__ s32, int64_t beg,
+                                                    const float *__restrict__ s32,
+                                                    const float *lt, int sh, int64_t beg,
                                                     int64_t end, int l) {
     double r = 0.0;
     for (int64_t e0 = beg + l; e0 < end; e0 += (int64_t)LANES * NI_DEPTH) {
-        float v[NI_DEPTH];
+        int32_t j[NI_DEPTH];
 #pragma unroll
         for (int q = 0; q < NI_DEPTH; ++q) {
             const int64_t e = e0 + (int64_t)q * LANES;
-            v[q] = e < end ? s32[icolidx[e]] : 0.f;
+            j[q] = e < end ? icolidx[e] : -1;
+        }
+        float v[NI_DEPTH];
+        if constexpr (TABLE) {
+#pragma unroll
+            for (int q = 0; q < NI_DEPTH; ++q) v[q] = j[q] >= 0 ? lt[j[q] >> sh] : 0.f;
+#pragma unroll
+            for (int q = 0; q < NI_DEPTH; ++q)
+                if (v[q] < 0.f) v[q] = s32[j[q]];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NI_DEPTH; ++q) v[q] = j[q] >= 0 ? s32[j[q]] : 0.f;
         }
 #pragma unroll
         for (int q = 0; q < NI_DEPTH; ++q) r += (double)v[q];
@@ -335,32 +378,45 @@ __device__ __forceinline__ double row_neighbour_sum(const int32_t *__restrict__ 
     return r;
 }
 
+// Row groups: heavy_groups of THREADS/64 heavy rows, then groups of
+// THREADS/NI_LANES light rows; with the table each block loads it once and
+// strides over the groups, without it a block takes one group.
+template <bool TABLE>
 __global__ __launch_bounds__(THREADS) void nodeinfo_kernel(int64_t N, int64_t n_heavy,
-                                                           int64_t heavy_blocks,
+                                                           int64_t heavy_groups, int64_t groups,
                                                            const int64_t *__restrict__ irowptr,
                                                            const int32_t *__restrict__ icolidx,
                                                            const double *__restrict__ s64,
                                                            const float *__restrict__ s32,
-                                                           double tau, double eps,
+                                                           const float *__restrict__ tab,
+                                                           int ntab, int sh, double tau,
+                                                           double eps,
                                                            float4 *__restrict__ info) {
-    int64_t k;
-    int l;
-    double r;
-    const int64_t blk = block_index();  // past the last block: k >= N below
-    if (blk < heavy_blocks) {
-        k = blk * (THREADS / 64) + threadIdx.x / 64;
-        l = threadIdx.x % 64;
-        if (k >= n_heavy) return;   // whole wave leaves together
-        r = row_neighbour_sum<64>(icolidx, s32, irowptr[k], irowptr[k + 1], l);
-    } else {
-        k = n_heavy + (blk - heavy_blocks) * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
-        l = threadIdx.x % NI_LANES;
-        if (k >= N) return;         // whole subgroup leaves together
-        r = row_neighbour_sum<NI_LANES>(icolidx, s32, irowptr[k], irowptr[k + 1], l);
+    __shared__ float lt[TABLE ? NI_TABLE : 1];
+    if constexpr (TABLE) {
+        for (int i = threadIdx.x; i < ntab; i += THREADS) lt[i] = tab[i];
+        __syncthreads();
     }
-    if (l == 0) {
-        const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
-        info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        int64_t k;
+        int l;
+        double r;
+        if (grp < heavy_groups) {
+            k = grp * (THREADS / 64) + threadIdx.x / 64;
+            l = threadIdx.x % 64;
+            if (k >= n_heavy) continue;   // the whole wave
+            r = row_neighbour_sum<64, TABLE>(icolidx, s32, lt, sh, irowptr[k], irowptr[k + 1], l);
+        } else {
+            k = n_heavy + (grp - heavy_groups) * (THREADS / NI_LANES) + threadIdx.x / NI_LANES;
+            l = threadIdx.x % NI_LANES;
+            if (k >= N) continue;         // the whole subgroup
+            r = row_neighbour_sum<NI_LANES, TABLE>(icolidx, s32, lt, sh, irowptr[k], irowptr[k + 1],
+                                                   l);
+        }
+        if (l == 0) {
+            const double dt = dtau_of((double)(irowptr[k + 1] - irowptr[k]), tau, eps);
+            info[k] = make_float4((float)s64[k], (float)sqrt(dt), (float)r, 0.0f);
+        }
     }
 }
 
@@ -955,11 +1011,26 @@ ifgp_status launch_nodeinfo(ifgp_graph_s *h, double tau, double eps, hipStream_t
     Scales &sc = h->sc;
     const GraphData &g = h->g;
     const int64_t n_heavy = g.n_hub + g.n_med;
-    const int64_t heavy_blocks = ceil_div(n_heavy, THREADS / 64);
-    const int64_t light_blocks = ceil_div(g.N - n_heavy, THREADS / NI_LANES);
-    nodeinfo_kernel<<<grid_for(heavy_blocks + light_blocks), THREADS, 0, s>>>(
-        g.N, n_heavy, heavy_blocks, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
-        sc.s64.as<double>(), sc.s32.as<float>(), tau, eps, sc.nodeinfo.as<float4>());
+    const int64_t heavy_groups = ceil_div(n_heavy, THREADS / 64);
+    const int64_t groups = heavy_groups + ceil_div(g.N - n_heavy, THREADS / NI_LANES);
+    if (g.N >= NI_TABLE_MIN_NODES) {
+        const int sh = ni_shift(g.N);
+        const int64_t ntab = ceil_div(g.N, (int64_t)1 << sh);
+        IFGP_TRY(ensure(sc.stab, sizeof(float) * NI_TABLE, s));
+        s_table_kernel<<<(unsigned)ceil_div(ntab, THREADS), THREADS, 0, s>>>(
+            g.N, sh, ntab, g.irowptr.as<int64_t>(), sc.s32.as<float>(), sc.stab.as<float>());
+        IFGP_LAUNCHED();
+        nodeinfo_kernel<true><<<(unsigned)std::min<int64_t>(groups, NI_GRID), THREADS, 0, s>>>(
+            g.N, n_heavy, heavy_groups, groups, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
+            sc.s64.as<double>(), sc.s32.as<float>(), sc.stab.as<float>(), (int)ntab, sh, tau, eps,
+            sc.nodeinfo.as<float4>());
+    } else {
+        // one block per group (N < 2^19: at most 2^17 groups)
+        nodeinfo_kernel<false><<<(unsigned)groups, THREADS, 0, s>>>(
+            g.N, n_heavy, heavy_groups, groups, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
+            sc.s64.as<double>(), sc.s32.as<float>(), nullptr, 0, 0, tau, eps,
+            sc.nodeinfo.as<float4>());
+    }
     IFGP_LAUNCHED();
     sc.tau = tau;
     sc.eps = eps;

@@ -76,6 +76,7 @@ struct Scales {
     Buf s64;       // double N: (D_tau)^{-1/2}
     Buf s32;       // float N: s64 rounded, gathered to form r
     Buf nodeinfo;  // float4 N: (s, sqrt(D_tau), sum_{j in N(i)} s_j, 0)
+    Buf stab;      // float: s per bucket of internal ids of one degree (-1: mixed)
 };
 
 struct Workspace {
