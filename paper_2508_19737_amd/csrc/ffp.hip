@@ -326,7 +326,8 @@ __global__ void scales_kernel(int64_t N, const int64_t *__restrict__ irowptr, do
 constexpr int NI_LANES = 8;
 constexpr int NI_DEPTH = 4;
 constexpr int NI_TABLE = 4096;      // buckets (16 KB of LDS)
-constexpr int64_t NI_GRID = 2048;   // blocks striding over the row groups
+constexpr int64_t NI_GRID = 1024;   // blocks striding over the row groups (4 per CU: room for the
+                                    // random input, which runs beside them)
 constexpr int64_t NI_TABLE_MIN_NODES = int64_t(1) << 19;
 
 int ni_shift(int64_t N) {
