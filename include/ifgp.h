@@ -138,6 +138,30 @@ IFGP_API ifgp_status ifgp_build_graph(const int64_t *src, const int64_t *dst, in
 IFGP_API ifgp_status ifgp_embed(ifgp_graph_t g, double tau, int32_t K, int32_t d, uint64_t seed,
                        const ifgp_params *p, float *out, void *hip_stream);
 
+/*
+ * ifgp_embed for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc): same
+ * arguments, same result, bit for bit.  Instead of the handle's buffers, the
+ * call works in a static device array of 64 MiB that the library holds on
+ * each device it runs on until the process ends: scales, two feature
+ * matrices, column statistics.  It calls no allocator (neither hipMalloc nor
+ * the allocator hook), creates no stream or event, and enqueues everything
+ * on hip_stream; hop timing (ifgp_timing_enable) does not apply to it.
+ * Limit: 28 N + 16 KiB + 2 N Dp b + 16 Dp (hop blocks) + 8 Dp bytes, each
+ * part rounded up to 256, must fit in 64 MiB (Dp = d padded to 8, 16, 32,
+ * 64, 128 or 256; b = 2 for BF16/FP16 storage, 4 for FP32): e.g. N up to
+ * about 220,000 at d = 64 in BF16, 115,000 in FP32.  Larger graphs return
+ * IFGP_E_INVALID before any work is enqueued.
+ * The array is shared: calls whose work overlaps on one device (other
+ * streams, other threads) race and give undefined results; calls ordered on
+ * one stream are safe, since each call rewrites every byte it reads.
+ * The handle's cached scales are neither used nor changed.
+ * Errors: as ifgp_embed (IFGP_E_OOM excepted).  Does not synchronise.
+ */
+IFGP_API ifgp_status ifgp_embed_noalloc(ifgp_graph_t g, double tau, int32_t K, int32_t d,
+                                        uint64_t seed, const ifgp_params *p, float *out,
+                                        void *hip_stream);
+
 /* As ifgp_embed with a caller-supplied Z^(0): X is device FP32 N x d
  * row-major (row i is node i).  It is read before the call's first hop. */
 IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t d, const float *X,

@@ -11,7 +11,8 @@ Public API (thin wrappers over the C ABI in include/ifgp.h):
     Birch(d, threshold)           BIRCH clustering of the embeddings (host
                                   CF-tree, device labelling)
 """
-from ._lib import (BF16, F16, F32, F64, EXPORTS, Birch, Graph, IfgpError, debug_grid_x,  # noqa: F401
+from ._lib import (BF16, E_DEVICE, E_INVALID, E_OOM, E_RANGE, E_STATE, F16, F32, F64, OK,  # noqa: F401
+                   EXPORTS, Birch, Graph, IfgpError, debug_grid_x,
                    embed_batch, empty_cache, footprint_bytes, gaussian_input, job_step, lib, params,
                    use_hip_allocator, use_torch_allocator, version)
 

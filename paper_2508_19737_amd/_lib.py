@@ -22,7 +22,8 @@ DTYPES = {"f32": F32, "fp32": F32, "float32": F32, "bf16": BF16, "bfloat16": BF1
 
 # Every entry point that include/ifgp.h declares.
 EXPORTS = [
-    "ifgp_default_params", "ifgp_build_graph", "ifgp_embed", "ifgp_embed_x",
+    "ifgp_default_params", "ifgp_build_graph", "ifgp_embed", "ifgp_embed_noalloc",
+    "ifgp_embed_x",
     "ifgp_gaussian_input", "ifgp_stream_add", "ifgp_embed_batch", "ifgp_job_begin",
     "ifgp_job_step", "ifgp_graph_info", "ifgp_plan_info", "ifgp_export_csr",
     "ifgp_export_scales",
@@ -60,6 +61,7 @@ def _load():
         "ifgp_default_params": [PP],
         "ifgp_build_graph": [P, P, i64, i64, ctypes.c_int, P, ctypes.POINTER(P)],
         "ifgp_embed": [P, f64, i32, i32, u64, PP, P, P],
+        "ifgp_embed_noalloc": [P, f64, i32, i32, u64, PP, P, P],
         "ifgp_embed_x": [P, f64, i32, i32, P, PP, P, P],
         "ifgp_gaussian_input": [i64, i32, u64, i32, P, P],
         "ifgp_stream_add": [P, P, P, i64, i64, ctypes.c_int, P],
@@ -269,6 +271,16 @@ class Graph:
         p = params(**kw)
         check(lib.ifgp_embed(self.handle, float(tau), int(K), int(d), ctypes.c_uint64(int(seed)),
                              ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def embed_noalloc(self, tau, K, d, seed, out, stream=None, **kw):
+        """ifgp_embed_noalloc: as embed, in the library's static device
+        scratch array (no device allocation; `out` must be given)."""
+        out = self._out(d, out)
+        p = params(**kw)
+        check(lib.ifgp_embed_noalloc(self.handle, float(tau), int(K), int(d),
+                                     ctypes.c_uint64(int(seed)), ctypes.byref(p),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def embed_x(self, tau, K, X, out=None, stream=None, **kw):

@@ -203,9 +203,12 @@ ifgp_status use_device(ifgp_graph_t g) {
 }
 
 // One whole embedding on g; on failure g is left with no job in progress.
+// `noalloc` runs it in the device's static scratch array (random input only).
 ifgp_status run_job(ifgp_graph_t g, double tau, int32_t K, int32_t d, uint64_t seed,
-                    const float *X, const ifgp_params &p, float *out, hipStream_t s) {
-    ifgp_status st = job_begin(g, tau, K, d, seed, X, p, out, s);
+                    const float *X, const ifgp_params &p, float *out, hipStream_t s,
+                    bool noalloc = false) {
+    ifgp_status st = noalloc ? job_begin_noalloc(g, tau, K, d, seed, p, out, s)
+                             : job_begin(g, tau, K, d, seed, X, p, out, s);
     while (st == IFGP_OK && !g->job.done) {
         ifgp_graph_s *one = g;
         st = jobs_step(&one, 1, s);
@@ -279,6 +282,16 @@ IFGP_API ifgp_status ifgp_embed(ifgp_graph_t g, double tau, int32_t K, int32_t d
     hipStream_t s = (hipStream_t)hip_stream;
     g->stream = s;
     return run_job(g, tau, K, d, seed, nullptr, resolve(p), out, s);
+}
+
+IFGP_API ifgp_status ifgp_embed_noalloc(ifgp_graph_t g, double tau, int32_t K, int32_t d,
+                                        uint64_t seed, const ifgp_params *p, float *out,
+                                        void *hip_stream) {
+    IFGP_TRY(check_handle(g));
+    IFGP_TRY(use_device(g));
+    hipStream_t s = (hipStream_t)hip_stream;
+    g->stream = s;
+    return run_job(g, tau, K, d, seed, nullptr, resolve(p), out, s, true);
 }
 
 IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t d, const float *X,

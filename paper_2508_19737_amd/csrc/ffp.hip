@@ -800,11 +800,11 @@ HopArgs make_hop_args(ifgp_graph_s *h) {
     HopArgs a{};
     a.rowptr = g.irowptr.as<int64_t>();
     a.colidx = g.icolidx.as<int32_t>();
-    a.Win = h->ws.feat[j.cur].p;
-    a.Wout = h->ws.feat[1 - j.cur].p;
-    a.node = h->sc.nodeinfo.as<float4>();
-    a.ab = h->ws.ab.as<float>();
-    a.partials = h->ws.partials.as<double2>();
+    a.Win = h->mem.feat[j.cur];
+    a.Wout = h->mem.feat[1 - j.cur];
+    a.node = h->mem.node;
+    a.ab = h->mem.ab;
+    a.partials = h->mem.partials;
     a.N = g.N;
     a.n_hub = g.n_hub;
     a.n_med = g.n_med;
@@ -819,12 +819,12 @@ HopArgs make_hop_args(ifgp_graph_s *h) {
 
 FinArgs make_fin_args(ifgp_graph_s *h) {
     FinArgs f{};
-    f.partials = h->ws.partials.as<double2>();
+    f.partials = h->mem.partials;
     f.blocks = hop_blocks(h->g, h->job.Dp, h->job.storage);
     f.N = h->g.N;
     f.D = h->job.Dp;
     f.ddof = h->job.ddof;
-    f.ab = h->ws.ab.as<float>();
+    f.ab = h->mem.ab;
     return f;
 }
 
@@ -901,9 +901,9 @@ ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStre
     const int64_t n = h->g.N * j.Dp;
     const dim3 grid = grid_for(ceil_div(n, THREADS));
     const dim3 grid4 = grid_for(ceil_div(n / 4, THREADS));
-    void *W = h->ws.feat[0].p;
+    void *W = h->mem.feat[0];
     const int32_t *perm = h->g.perm.as<int32_t>();
-    const double *s64 = h->sc.s64.as<double>();
+    const double *s64 = h->mem.s64;
     const int64_t N = h->g.N;
     const int d = j.d;
 #define NOISE_CALL(T, D)                                                                        \
@@ -918,9 +918,9 @@ ifgp_status launch_noise(ifgp_graph_s *h, uint64_t seed, const float *X, hipStre
 ifgp_status launch_epilogue(ifgp_graph_s *h, hipStream_t s) {
     const Job &j = h->job;
     const int64_t N = h->g.N;
-    const void *W = h->ws.feat[j.cur].p;
-    const float4 *node = h->sc.nodeinfo.as<float4>();
-    const float *ab = h->ws.ab.as<float>();
+    const void *W = h->mem.feat[j.cur];
+    const float4 *node = h->mem.node;
+    const float *ab = h->mem.ab;
     const int32_t *perm = h->g.perm.as<int32_t>();
     float *out = j.out;
     const int d = j.d;
@@ -952,7 +952,7 @@ ifgp_status validate_params(const ifgp_params &p) {
 }
 
 ifgp_status record_event(ifgp_graph_s *h, hipStream_t s, bool start) {
-    if (!h->timing) return IFGP_OK;
+    if (!h->timing || h->job.noalloc) return IFGP_OK;
     hipEvent_t ev;
     IFGP_HIP(hipEventCreate(&ev));
     IFGP_HIP(hipEventRecord(ev, s));
@@ -994,49 +994,66 @@ ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t d
 }
 
 namespace {
-// s in FP64 and FP32 (cheap); node info (the neighbour sums r) follows.
-ifgp_status launch_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
-    Scales &sc = h->sc;
-    const GraphData &g = h->g;
-    sc.valid = false;
-    IFGP_TRY(ensure(sc.s64, sizeof(double) * g.N, s));
-    IFGP_TRY(ensure(sc.s32, sizeof(float) * g.N, s));
-    IFGP_TRY(ensure(sc.nodeinfo, sizeof(float4) * g.N, s));
+// s in FP64 and FP32 (cheap) into m.s64, m.s32; the node info (the neighbour
+// sums r) follows from them.
+ifgp_status launch_scales(const GraphData &g, const EmbedMem &m, double tau, double eps,
+                          hipStream_t s) {
     scales_kernel<<<grid_for(ceil_div(g.N, THREADS)), THREADS, 0, s>>>(
-        g.N, g.irowptr.as<int64_t>(), tau, eps, sc.s64.as<double>(), sc.s32.as<float>());
+        g.N, g.irowptr.as<int64_t>(), tau, eps, m.s64, m.s32);
     IFGP_LAUNCHED();
     return IFGP_OK;
 }
 
-ifgp_status launch_nodeinfo(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
-    Scales &sc = h->sc;
-    const GraphData &g = h->g;
+ifgp_status launch_nodeinfo(const GraphData &g, const EmbedMem &m, double tau, double eps,
+                            hipStream_t s) {
     const int64_t n_heavy = g.n_hub + g.n_med;
     const int64_t heavy_groups = ceil_div(n_heavy, THREADS / 64);
     const int64_t groups = heavy_groups + ceil_div(g.N - n_heavy, THREADS / NI_LANES);
     if (g.N >= NI_TABLE_MIN_NODES) {
         const int sh = ni_shift(g.N);
         const int64_t ntab = ceil_div(g.N, (int64_t)1 << sh);
-        IFGP_TRY(ensure(sc.stab, sizeof(float) * NI_TABLE, s));
         s_table_kernel<<<(unsigned)ceil_div(ntab, THREADS), THREADS, 0, s>>>(
-            g.N, sh, ntab, g.irowptr.as<int64_t>(), sc.s32.as<float>(), sc.stab.as<float>());
+            g.N, sh, ntab, g.irowptr.as<int64_t>(), m.s32, m.stab);
         IFGP_LAUNCHED();
         nodeinfo_kernel<true><<<(unsigned)std::min<int64_t>(groups, NI_GRID), THREADS, 0, s>>>(
             g.N, n_heavy, heavy_groups, groups, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
-            sc.s64.as<double>(), sc.s32.as<float>(), sc.stab.as<float>(), (int)ntab, sh, tau, eps,
-            sc.nodeinfo.as<float4>());
+            m.s64, m.s32, m.stab, (int)ntab, sh, tau, eps, m.node);
     } else {
         // one block per group (N < 2^19: at most 2^17 groups)
         nodeinfo_kernel<false><<<(unsigned)groups, THREADS, 0, s>>>(
             g.N, n_heavy, heavy_groups, groups, g.irowptr.as<int64_t>(), g.icolidx.as<int32_t>(),
-            sc.s64.as<double>(), sc.s32.as<float>(), nullptr, 0, 0, tau, eps,
-            sc.nodeinfo.as<float4>());
+            m.s64, m.s32, nullptr, 0, 0, tau, eps, m.node);
     }
     IFGP_LAUNCHED();
+    return IFGP_OK;
+}
+
+// The handle's cached scales: buffers sized for the graph (invalid until
+// their node info is launched).
+ifgp_status ensure_scale_bufs(ifgp_graph_s *h, hipStream_t s) {
+    Scales &sc = h->sc;
+    const int64_t N = h->g.N;
+    sc.valid = false;
+    IFGP_TRY(ensure(sc.s64, sizeof(double) * N, s));
+    IFGP_TRY(ensure(sc.s32, sizeof(float) * N, s));
+    IFGP_TRY(ensure(sc.nodeinfo, sizeof(float4) * N, s));
+    if (N >= NI_TABLE_MIN_NODES) IFGP_TRY(ensure(sc.stab, sizeof(float) * NI_TABLE, s));
+    return IFGP_OK;
+}
+
+EmbedMem scale_view(const Scales &sc) {
+    EmbedMem m;
+    m.s64 = sc.s64.as<double>();
+    m.s32 = sc.s32.as<float>();
+    m.node = sc.nodeinfo.as<float4>();
+    m.stab = sc.stab.as<float>();
+    return m;
+}
+
+void mark_scales(Scales &sc, double tau, double eps) {
     sc.tau = tau;
     sc.eps = eps;
     sc.valid = true;
-    return IFGP_OK;
 }
 
 bool scales_cached(const ifgp_graph_s *h, double tau, double eps) {
@@ -1074,8 +1091,17 @@ ifgp_status ensure_side_stream(ifgp_graph_s *h) { return ensure_aux(h); }
 
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
     if (scales_cached(h, tau, eps)) return IFGP_OK;
-    IFGP_TRY(launch_scales(h, tau, eps, s));
-    return launch_nodeinfo(h, tau, eps, s);
+    if (h->job.active && !h->job.done && !h->job.noalloc) {
+        // the unfinished job's hops read the cached node info
+        set_error("the graph has an unfinished job with other scales");
+        return IFGP_E_STATE;
+    }
+    IFGP_TRY(ensure_scale_bufs(h, s));
+    const EmbedMem m = scale_view(h->sc);
+    IFGP_TRY(launch_scales(h->g, m, tau, eps, s));
+    IFGP_TRY(launch_nodeinfo(h->g, m, tau, eps, s));
+    mark_scales(h->sc, tau, eps);
+    return IFGP_OK;
 }
 
 ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s) {
@@ -1090,8 +1116,15 @@ ifgp_status scales_to_host(ifgp_graph_s *h, double *s_host, hipStream_t s) {
     return IFGP_OK;
 }
 
-ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
-                      const float *X, const ifgp_params &p, float *out, hipStream_t s) {
+// Device memory that only the allocation-free entry point uses
+// (NOALLOC_SCRATCH_BYTES).  Each device holds its own copy for the life of the
+// process.  Host code never uses this name as an address: it reaches the
+// array only through the pointer hipGetSymbolAddress returns for the current
+// device (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+ifgp_status check_job_args(double tau, int32_t K, int32_t d, const ifgp_params &p, float *out) {
     IFGP_TRY(validate_params(p));
     if (!std::isfinite(tau)) {
         set_error("tau must be finite");
@@ -1101,20 +1134,20 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
         set_error("need K >= 0, 1 <= d <= 256 and an output buffer");
         return IFGP_E_INVALID;
     }
-    const int Dp = padded_width(d);
-    h->job = Job{};
-    const bool fresh_scales = !scales_cached(h, tau, p.eps);
-    if (fresh_scales) IFGP_TRY(launch_scales(h, tau, p.eps, s));
+    return IFGP_OK;
+}
+
+// Launch the start of a job whose buffers are in h->mem: the scales if
+// fresh_scales (their node info may overlap the random input on the side
+// stream when `overlap`), Z^(0), a = 1, b = 0, and at K = 0 the output.
+ifgp_status job_start(ifgp_graph_s *h, bool fresh_scales, bool overlap, double tau, int32_t K,
+                      int32_t d, uint64_t seed, const float *X, const ifgp_params &p, float *out,
+                      hipStream_t s) {
     const GraphData &g = h->g;
-    const size_t fb = (size_t)g.N * Dp * dtype_bytes(p.storage);
-    IFGP_TRY(ensure(h->ws.feat[0], fb, s));
-    IFGP_TRY(ensure(h->ws.feat[1], fb, s));
-    IFGP_TRY(ensure(h->ws.partials, sizeof(double2) * Dp * hop_blocks(g, Dp, p.storage), s));
-    IFGP_TRY(ensure(h->ws.ab, sizeof(float) * 2 * Dp, s));
     Job &j = h->job;
     j.K = K;
     j.d = d;
-    j.Dp = Dp;
+    j.Dp = padded_width(d);
     j.hop = 0;
     j.storage = p.storage;
     j.alpha = p.alpha;
@@ -1122,7 +1155,8 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
     j.ddof = p.znorm_ddof;
     j.cur = 0;
     j.out = out;
-    if (fresh_scales && !X && g.N >= OVERLAP_MIN_NODES) {
+    if (fresh_scales) IFGP_TRY(launch_scales(g, h->mem, tau, p.eps, s));
+    if (fresh_scales && overlap && !X && g.N >= OVERLAP_MIN_NODES) {
         // The random input needs only s; it is arithmetic-bound while the
         // neighbour sums are gather-bound, so run them side by side.
         IFGP_TRY(ensure_aux(h));
@@ -1131,14 +1165,14 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
         IFGP_TRY(launch_noise(h, seed, X, h->aux));
         IFGP_LAUNCHED();
         IFGP_HIP(hipEventRecord(h->ev_join, h->aux));
-        IFGP_TRY(launch_nodeinfo(h, tau, p.eps, s));
+        IFGP_TRY(launch_nodeinfo(g, h->mem, tau, p.eps, s));
         IFGP_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     } else {
-        if (fresh_scales) IFGP_TRY(launch_nodeinfo(h, tau, p.eps, s));
+        if (fresh_scales) IFGP_TRY(launch_nodeinfo(g, h->mem, tau, p.eps, s));
         IFGP_TRY(launch_noise(h, seed, X, s));
         IFGP_LAUNCHED();
     }
-    ab_identity_kernel<<<1, THREADS, 0, s>>>(h->ws.ab.as<float>(), Dp);
+    ab_identity_kernel<<<1, THREADS, 0, s>>>(h->mem.ab, j.Dp);
     IFGP_LAUNCHED();
     j.active = true;
     if (K == 0) {
@@ -1147,6 +1181,108 @@ ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_
         j.done = true;
     }
     return IFGP_OK;
+}
+
+// The allocation-free embedding's buffers, carved in this order out of the
+// static array, each starting on a 256-byte boundary.
+struct ScratchLayout {
+    size_t s64, s32, node, stab, feat0, feat1, partials, ab, total;
+};
+
+ScratchLayout scratch_layout(int64_t N, int Dp, int storage, int64_t blocks) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    ScratchLayout L{};
+    size_t o = 0;
+    L.s64 = o;      o += up(sizeof(double) * N);
+    L.s32 = o;      o += up(sizeof(float) * N);
+    L.node = o;     o += up(sizeof(float4) * N);
+    L.stab = o;     o += up(sizeof(float) * NI_TABLE);
+    const size_t fb = up((size_t)N * Dp * dtype_bytes(storage));
+    L.feat0 = o;    o += fb;
+    L.feat1 = o;    o += fb;
+    L.partials = o; o += up(sizeof(double2) * Dp * blocks);
+    L.ab = o;       o += up(sizeof(float) * 2 * Dp);
+    L.total = o;
+    return L;
+}
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[64] = {};
+
+// The scratch array's address on `device`, which must be current.
+ifgp_status scratch_address(int device, unsigned char **out) {
+    if (device < 0 || device >= 64) {
+        set_error("device index out of range");
+        return IFGP_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        IFGP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("hipGetSymbolAddress returned no address for the scratch array");
+            return IFGP_E_DEVICE;
+        }
+        g_scratch_dev[device] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_dev[device]);
+    return IFGP_OK;
+}
+}  // namespace
+
+ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
+                      const float *X, const ifgp_params &p, float *out, hipStream_t s) {
+    IFGP_TRY(check_job_args(tau, K, d, p, out));
+    const int Dp = padded_width(d);
+    h->job = Job{};
+    const bool fresh_scales = !scales_cached(h, tau, p.eps);
+    if (fresh_scales) IFGP_TRY(ensure_scale_bufs(h, s));
+    const GraphData &g = h->g;
+    const size_t fb = (size_t)g.N * Dp * dtype_bytes(p.storage);
+    IFGP_TRY(ensure(h->ws.feat[0], fb, s));
+    IFGP_TRY(ensure(h->ws.feat[1], fb, s));
+    IFGP_TRY(ensure(h->ws.partials, sizeof(double2) * Dp * hop_blocks(g, Dp, p.storage), s));
+    IFGP_TRY(ensure(h->ws.ab, sizeof(float) * 2 * Dp, s));
+    EmbedMem m = scale_view(h->sc);
+    m.feat[0] = h->ws.feat[0].p;
+    m.feat[1] = h->ws.feat[1].p;
+    m.partials = h->ws.partials.as<double2>();
+    m.ab = h->ws.ab.as<float>();
+    h->mem = m;
+    IFGP_TRY(job_start(h, fresh_scales, true, tau, K, d, seed, X, p, out, s));
+    if (fresh_scales) mark_scales(h->sc, tau, p.eps);
+    return IFGP_OK;
+}
+
+ifgp_status job_begin_noalloc(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
+                              const ifgp_params &p, float *out, hipStream_t s) {
+    IFGP_TRY(check_job_args(tau, K, d, p, out));
+    const int Dp = padded_width(d);
+    const GraphData &g = h->g;
+    const ScratchLayout L = scratch_layout(g.N, Dp, p.storage, hop_blocks(g, Dp, p.storage));
+    if (L.total > NOALLOC_SCRATCH_BYTES) {
+        set_error("ifgp_embed_noalloc: N = %lld at width %d in this storage needs %zu bytes of "
+                  "scratch, above the limit of %zu",
+                  (long long)g.N, Dp, L.total, NOALLOC_SCRATCH_BYTES);
+        return IFGP_E_INVALID;
+    }
+    unsigned char *base = nullptr;
+    IFGP_TRY(scratch_address(h->device, &base));
+    h->job = Job{};
+    EmbedMem m;
+    m.s64 = reinterpret_cast<double *>(base + L.s64);
+    m.s32 = reinterpret_cast<float *>(base + L.s32);
+    m.node = reinterpret_cast<float4 *>(base + L.node);
+    m.stab = reinterpret_cast<float *>(base + L.stab);
+    m.feat[0] = base + L.feat0;
+    m.feat[1] = base + L.feat1;
+    m.partials = reinterpret_cast<double2 *>(base + L.partials);
+    m.ab = reinterpret_cast<float *>(base + L.ab);
+    h->mem = m;
+    h->job.noalloc = true;
+    // the scales are recomputed into the scratch array; the handle's cached
+    // ones are neither read nor touched
+    return job_start(h, true, false, tau, K, d, seed, nullptr, p, out, s);
 }
 
 ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s) {

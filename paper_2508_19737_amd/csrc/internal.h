@@ -85,6 +85,19 @@ struct Workspace {
     Buf ab;         // float [2][Dp]: per-column scale a = 1/sigma and shift b = -mu/sigma
 };
 
+// The device memory one embedding works in, as plain pointers: the handle's
+// own buffers (Scales, Workspace) or a carved-up region of the library's
+// static scratch array (the allocation-free entry point).
+struct EmbedMem {
+    double *s64 = nullptr;
+    float *s32 = nullptr;
+    float4 *node = nullptr;
+    float *stab = nullptr;
+    void *feat[2] = {nullptr, nullptr};
+    double2 *partials = nullptr;
+    float *ab = nullptr;
+};
+
 struct Job {
     bool active = false;
     int32_t K = 0, d = 0, Dp = 0, hop = 0;
@@ -94,6 +107,7 @@ struct Job {
     int cur = 0;      // which feat buffer holds the current hop's input
     float *out = nullptr;
     bool done = false;
+    bool noalloc = false;   // runs in the static scratch array: no events, no side stream
 };
 
 }  // namespace ifgp
@@ -106,6 +120,7 @@ struct ifgp_graph_s {
     ifgp::GraphData g;
     ifgp::Scales sc;
     ifgp::Workspace ws;
+    ifgp::EmbedMem mem;             // what the current job's kernels read and write
     ifgp::Job job;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -134,6 +149,12 @@ ifgp_status ensure_side_stream(ifgp_graph_s *h);
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s);
 ifgp_status job_begin(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
                       const float *X, const ifgp_params &p, float *out, hipStream_t s);
+// As job_begin (random input only) with every buffer carved out of the
+// device's static scratch array: no allocation, no side stream, no events.
+// IFGP_E_INVALID if the embedding needs more than NOALLOC_SCRATCH_BYTES.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+ifgp_status job_begin_noalloc(ifgp_graph_s *h, double tau, int32_t K, int32_t d, uint64_t seed,
+                              const ifgp_params &p, float *out, hipStream_t s);
 // Advance every listed job by one hop (one launch per storage/width class).
 ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s);
 int64_t hop_blocks(const GraphData &g, int Dp, int storage);
