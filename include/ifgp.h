@@ -163,14 +163,17 @@ IFGP_API ifgp_status ifgp_embed_noalloc(ifgp_graph_t g, double tau, int32_t K, i
                                         void *hip_stream);
 
 /* As ifgp_embed with a caller-supplied Z^(0): X is device FP32 N x d
- * row-major (row i is node i).  It is read before the call's first hop. */
+ * row-major (row i is node i).  It is read before the call's first hop: the
+ * first hop's input row s_i X[i] is formed in FP64 and rounded to the storage
+ * type (once for FP32 and FP16, through FP32 for BF16). */
 IFGP_API ifgp_status ifgp_embed_x(ifgp_graph_t g, double tau, int32_t K, int32_t d, const float *X,
                          const ifgp_params *p, float *out, void *hip_stream);
 
 /*
  * The random input alone: out[i, c] = Z^(0)[i, c] for 0 <= i < N, 0 <= c < d,
- * by the rule given at ifgp_embed, rounded once to `dtype` (F64, F32, BF16 or
- * F16).  out is device memory, N x d row-major.  Errors: IFGP_E_INVALID.
+ * by the rule given at ifgp_embed (in FP64), rounded to `dtype` (F64, F32,
+ * BF16 or F16): once for F32 and F16, through FP32 for BF16.  out is device
+ * memory, N x d row-major.  Errors: IFGP_E_INVALID.
  */
 IFGP_API ifgp_status ifgp_gaussian_input(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
                                 void *hip_stream);
@@ -280,6 +283,21 @@ IFGP_API ifgp_status ifgp_timing_read(ifgp_graph_t g, int64_t *hop_launches, dou
  */
 IFGP_API ifgp_status ifgp_debug_grid_x(int64_t max_x_blocks, int64_t *previous);
 
+/*
+ * Test hook for the hop kernel's gather depth (the neighbour rows each lane
+ * keeps in flight), which is otherwise chosen per graph from the size of its
+ * feature matrix (2-byte storage only; FP32 storage has one depth):
+ *   -1  per graph (the default): 16 rows if the matrix fits in 32 MiB, 4 if it
+ *       reaches 224 MiB with rows of 64 or more columns, 8 otherwise
+ *    0  8 rows      1  4 rows (rows of 64 or more columns; narrower rows use 8)
+ *    2  16 rows
+ * Results of a hop may differ between depths only in the order of the FP32
+ * additions.  *previous (may be NULL) receives the setting in force before
+ * the call.  Other values: IFGP_E_INVALID.  Process-wide; not for use while
+ * other threads launch work.
+ */
+IFGP_API ifgp_status ifgp_debug_hop_depth(int32_t depth, int32_t *previous);
+
 /* Release the handle and all its device memory (NULL is accepted). */
 IFGP_API ifgp_status ifgp_destroy(ifgp_graph_t g);
 
@@ -342,6 +360,25 @@ IFGP_API ifgp_status ifgp_birch_centers(ifgp_birch_t b, double *centers);
  * hip_stream synchronised) on first use after a change of the tree. */
 IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t n,
                                         int32_t *labels, void *hip_stream);
+
+/*
+ * The labels ifgp_birch_predict gives (bit for bit), for Algorithm 2's use:
+ * between calls on one tree the rows labelled by the previous call keep their
+ * values and new rows follow them (rows 0 .. m-1 of Z hold what they held in
+ * the previous call, m = that call's n <= n; n < m starts over).  The call
+ * compares each old row only with the cluster centroids created or changed
+ * since the previous call (its nearest entry is otherwise unchanged), unless
+ * that row's nearest entry itself changed; distances are taken in FP32 on the
+ * matrix cores with a rigorous bound on their difference from the FP64 ones,
+ * and rows whose nearest and second-nearest entries lie within that bound are
+ * labelled in FP64 by ifgp_birch_predict's rule (first index on ties).  The
+ * centroids and what is known of each row stay in device memory held by the
+ * tree (about 16 bytes per row and 12 Dp per cluster, Dp = d rounded up to
+ * 8, 16, 32 or 64).  Z: device, n x d FP32,
+ * d <= 64; labels: device int32 n.  Errors as ifgp_birch_predict.
+ */
+IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, int64_t n,
+                                               int32_t *labels, void *hip_stream);
 
 /* Release the tree and its device copy (NULL is accepted). */
 IFGP_API ifgp_status ifgp_birch_destroy(ifgp_birch_t b);

@@ -12,7 +12,7 @@ Public API (thin wrappers over the C ABI in include/ifgp.h):
                                   CF-tree, device labelling)
 """
 from ._lib import (BF16, E_DEVICE, E_INVALID, E_OOM, E_RANGE, E_STATE, F16, F32, F64, OK,  # noqa: F401
-                   EXPORTS, Birch, Graph, IfgpError, debug_grid_x,
+                   EXPORTS, Birch, Graph, IfgpError, debug_grid_x, debug_hop_depth,
                    embed_batch, empty_cache, footprint_bytes, gaussian_input, job_step, lib, params,
                    use_hip_allocator, use_torch_allocator, version)
 

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libifgp.so")
+# IFGP_LIBRARY may name another build of the same library (the sanitizer
+# build, libifgp_san.so); by default the one built in this directory.
+LIB_PATH = os.environ.get("IFGP_LIBRARY") or os.path.join(_HERE, "libifgp.so")
 
 OK, E_INVALID, E_RANGE, E_OOM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
 F32, BF16, F16, F64 = 0, 1, 2, 3
@@ -28,10 +30,10 @@ EXPORTS = [
     "ifgp_job_step", "ifgp_graph_info", "ifgp_plan_info", "ifgp_export_csr",
     "ifgp_export_scales",
     "ifgp_footprint_bytes", "ifgp_set_allocator", "ifgp_empty_cache", "ifgp_timing_enable",
-    "ifgp_timing_read", "ifgp_debug_grid_x",
+    "ifgp_timing_read", "ifgp_debug_grid_x", "ifgp_debug_hop_depth",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
     "ifgp_birch_create", "ifgp_birch_partial_fit", "ifgp_birch_info", "ifgp_birch_centers",
-    "ifgp_birch_predict", "ifgp_birch_destroy",
+    "ifgp_birch_predict", "ifgp_birch_predict_update", "ifgp_birch_destroy",
 ]
 
 
@@ -78,12 +80,14 @@ def _load():
         "ifgp_timing_enable": [P, ctypes.c_int],
         "ifgp_timing_read": [P, P, P],
         "ifgp_debug_grid_x": [i64, P],
+        "ifgp_debug_hop_depth": [i32, P],
         "ifgp_destroy": [P],
         "ifgp_birch_create": [i32, f64, i32, ctypes.POINTER(P)],
         "ifgp_birch_partial_fit": [P, P, i64, ctypes.c_int, P],
         "ifgp_birch_info": [P, P, P, P],
         "ifgp_birch_centers": [P, P],
         "ifgp_birch_predict": [P, P, i64, P, P],
+        "ifgp_birch_predict_update": [P, P, i64, P, P],
         "ifgp_birch_destroy": [P],
     }
     for name, args in sig.items():
@@ -182,6 +186,14 @@ def debug_grid_x(max_x_blocks: int) -> int:
     max_x_blocks blocks (0 = the default); returns the previous cap."""
     prev = ctypes.c_int64()
     check(lib.ifgp_debug_grid_x(int(max_x_blocks), ctypes.byref(prev)))
+    return prev.value
+
+
+def debug_hop_depth(depth: int) -> int:
+    """Test hook: force the hop's gather depth for 2-byte storage (0: 8 rows
+    in flight, 1: 4, 2: 16; -1: chosen per graph); returns the previous."""
+    prev = ctypes.c_int32()
+    check(lib.ifgp_debug_hop_depth(int(depth), ctypes.byref(prev)))
     return prev.value
 
 
@@ -432,6 +444,23 @@ class Birch:
             raise ValueError("out must be a contiguous int32 CUDA tensor of shape (n,)")
         check(lib.ifgp_birch_predict(self._live(), ctypes.c_void_p(Zt.data_ptr()), Zt.shape[0],
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def predict_update(self, Z, out=None, stream=None):
+        """ifgp_birch_predict_update: the labels predict gives, for rows that
+        extend those of the previous call of this method (Algorithm 2)."""
+        torch = _torch()
+        Zt = Z.detach().to(torch.float32).contiguous()
+        if Zt.dim() != 2 or Zt.shape[1] != self.d or not Zt.is_cuda:
+            raise IfgpError(E_INVALID, f"Z must be a GPU tensor n x {self.d}")
+        if out is None:
+            out = torch.empty(Zt.shape[0], dtype=torch.int32, device=Zt.device)
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() \
+                or tuple(out.shape) != (Zt.shape[0],):
+            raise ValueError("out must be a contiguous int32 CUDA tensor of shape (n,)")
+        check(lib.ifgp_birch_predict_update(self._live(), ctypes.c_void_p(Zt.data_ptr()),
+                                            Zt.shape[0], ctypes.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream)))
         return out
 
     def fit_predict(self, Z, stream=None):

@@ -515,6 +515,16 @@ IFGP_API ifgp_status ifgp_debug_grid_x(int64_t max_x_blocks, int64_t *previous) 
     return IFGP_OK;
 }
 
+IFGP_API ifgp_status ifgp_debug_hop_depth(int32_t depth, int32_t *previous) {
+    if (depth < -1 || depth > 2) {
+        set_error("ifgp_debug_hop_depth: depth must be -1, 0, 1 or 2");
+        return IFGP_E_INVALID;
+    }
+    const int prev = force_hop_depth(depth);
+    if (previous) *previous = prev;
+    return IFGP_OK;
+}
+
 IFGP_API ifgp_status ifgp_timing_enable(ifgp_graph_t g, int enable) {
     IFGP_TRY(check_handle(g));
     g->timing = enable != 0;

@@ -38,6 +38,8 @@ struct BNode {
                               // ct[((k / NB) * d + j) * NB + k % NB]
     int cap = 0;              // entries ct has room for (B + 1 rounded up to a block)
     std::vector<BNode *> child;
+    std::vector<int32_t> id;  // per entry: the leaf entry's identity (-1 in inner nodes); it
+                              // stays with the entry when a split moves it to another leaf
     BNode *prev_leaf = nullptr, *next_leaf = nullptr;
     int size() const { return (int)n.size(); }
 };
@@ -124,6 +126,43 @@ bool use_avx2() {
 
 
 }  // namespace
+
+// Device state of ifgp_birch_predict_update: the centroids in slots by entry
+// identity (an entry keeps its slot while splits move it through the leaf
+// order), what is known of every point labelled so far, and work lists.
+struct LabelState {
+    Buf f32, f64;          // slot fragments: block cb (identities 16 cb ... 16 cb + 15),
+                           // coordinate step s: 64 values in lane order
+    Buf cn32, cn64;        // |c|^2 per slot, +inf in unused slots
+    int64_t cap_blk = 0;   // blocks the slot arrays hold
+    Buf idx;               // int32 per identity: the entry's index in leaf order
+    Buf chg;               // uint8 per identity: centroid new or changed since the last update
+    Buf cmp;               // the changed entries, packed: FP32 fragments (blocks of 16), FP32
+                           // norms, identities
+    int64_t cmp_blk = 0;   // blocks cmp holds
+    Buf raw;               // the changed entries as uploaded: FP64 centroids, norms, identities
+    Buf best_id;           // int32 per point: its entry, by identity
+    Buf best32;            // float per point: FP32 distance to that entry, NaN if not known
+    Buf lists;             // int32 [2][cap_pts]: points to redo in FP32, then in FP64
+    Buf counters;          // int32 [2]: the two lists' lengths
+    int64_t cap_pts = 0, n_prev = 0;
+    bool slots_valid = false;
+    void *stage = nullptr;  // pinned host staging of an upload
+    size_t stage_bytes = 0;
+    LabelState() = default;
+    LabelState(const LabelState &) = delete;
+    LabelState &operator=(const LabelState &) = delete;
+    ~LabelState() {
+        if (stage) (void)hipHostFree(stage);
+    }
+    void reset() {
+        f32.reset(); f64.reset(); cn32.reset(); cn64.reset(); idx.reset(); chg.reset();
+        cmp.reset(); raw.reset(); best_id.reset(); best32.reset(); lists.reset();
+        counters.reset();
+        cap_blk = cmp_blk = cap_pts = n_prev = 0;
+        slots_valid = false;
+    }
+};
 }  // namespace ifgp
 
 struct ifgp_birch_s {
@@ -141,6 +180,13 @@ struct ifgp_birch_s {
     bool dirty = true;
     int device = -1;
     bool broken = false;  // a host allocation failed part-way through an insertion
+    // leaf entries are numbered 0, 1, ... as they are created (they are never
+    // removed); chg[id] marks those created, or whose centroid changed, since
+    // the last ifgp_birch_predict_update; chg_list lists them
+    int32_t next_id = 0;
+    std::vector<uint8_t> chg;
+    std::vector<int32_t> chg_list;
+    ifgp::LabelState ls;  // device state of ifgp_birch_predict_update
 };
 
 namespace ifgp {
@@ -159,6 +205,7 @@ BNode *new_node(ifgp_birch_s *t, bool leaf) {
     x->c.reserve((size_t)(t->B + 1) * t->d);
     x->cn.reserve(t->B + 1);
     x->child.reserve(t->B + 1);
+    x->id.reserve(t->B + 1);
     return x;
 }
 
@@ -173,7 +220,9 @@ void refresh(BNode *x, int k, int d) {
     x->cn[k] = dot(c, c, d);
 }
 
-void append(BNode *x, int d, int64_t n, const double *ls, double ss, BNode *child) {
+void append(BNode *x, int d, int64_t n, const double *ls, double ss, BNode *child,
+            int32_t id = -1) {
+    x->id.push_back(id);
     x->n.push_back(n);
     x->ls.insert(x->ls.end(), ls, ls + d);
     x->ss.push_back(ss);
@@ -239,7 +288,7 @@ std::pair<BNode *, BNode *> split(ifgp_birch_s *t, BNode *x) {
     BNode *a = new_node(t, x->leaf), *b = new_node(t, x->leaf);
     for (int i = 0; i < k; ++i) {
         const bool to_a = i == p || dist(p, i) < dist(q, i);
-        append(to_a ? a : b, d, x->n[i], &x->ls[(size_t)i * d], x->ss[i], x->child[i]);
+        append(to_a ? a : b, d, x->n[i], &x->ls[(size_t)i * d], x->ss[i], x->child[i], x->id[i]);
     }
     if (x->leaf) {
         a->prev_leaf = x->prev_leaf;
@@ -254,11 +303,26 @@ std::pair<BNode *, BNode *> split(ifgp_birch_s *t, BNode *x) {
     return {a, b};
 }
 
+// A leaf entry's centroid changed (or the entry is new).
+void mark_changed(ifgp_birch_s *t, int32_t id) {
+    if (!t->chg[(size_t)id]) {
+        t->chg[(size_t)id] = 1;
+        t->chg_list.push_back(id);
+    }
+}
+
+int32_t new_entry_id(ifgp_birch_s *t) {
+    const int32_t id = t->next_id++;
+    t->chg.push_back(0);
+    mark_changed(t, id);
+    return id;
+}
+
 // Insert point p (|p|^2 = pp) below x; true if x now holds more than B entries.
 bool insert(ifgp_birch_s *t, BNode *x, const double *p, double pp, std::vector<double> &tmp) {
     const int d = t->d;
     if (x->size() == 0) {
-        append(x, d, 1, p, pp, nullptr);
+        append(x, d, 1, p, pp, nullptr, new_entry_id(t));
         return false;
     }
     const int k = nearest(x, p, d);
@@ -296,9 +360,10 @@ bool insert(ifgp_birch_s *t, BNode *x, const double *p, double pp, std::vector<d
         std::memcpy(&x->ls[(size_t)k * d], ls1, sizeof(double) * d);
         x->ss[k] = ss1;
         refresh(x, k, d);
+        mark_changed(t, x->id[k]);
         return false;
     }
-    append(x, d, 1, p, pp, nullptr);
+    append(x, d, 1, p, pp, nullptr, new_entry_id(t));
     return x->size() > t->B;
 }
 
@@ -459,6 +524,468 @@ ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
     IFGP_HIP(hipStreamSynchronize(s));  // h is pageable and goes out of scope
     t->Dp = Dp;
     t->dirty = false;
+    return IFGP_OK;
+}
+
+
+// ---------------------------------------------------------------- labelling by update
+// ifgp_birch_predict_update gives the labels ifgp_birch_predict gives, for
+// Algorithm 2's pattern of use: the rows labelled by the previous call keep
+// their values and new rows follow them, while the tree changed in between
+// only where points were inserted.
+//
+// Distances are first taken in FP32 on the matrix cores (v_mfma_f32_16x16x4f32,
+// twice the FP64 rate) with a bound beta on their difference from the FP64
+// values the FP64 kernel would compare (beta below).  A point's nearest entry
+// is decided in FP32 when the runner-up is more than 2 beta further away:
+// then the FP64 order is the same.  Otherwise (ties, near ties) the point is
+// labelled by the FP64 kernel's rule, first index in leaf order on ties.
+//
+// A point labelled before whose nearest entry did not change keeps it against
+// every unchanged entry (they and the point are as they were), so it is
+// compared only with the entries created or changed since, under the same
+// rule; a point whose nearest entry changed, or that was decided in FP64, is
+// labelled again from scratch.
+//
+// Entries sit in slots by identity, so the device copy of the tree changes
+// only where entries changed; labels map identities to leaf-order indices at
+// the end.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// FP32 MFMA lane layout (checked on the device): lane l, slot r of the
+// 16 x 16 result holds D[4 (l / 16) + r][l % 16]; the operands are laid out as
+// for the FP64 instruction above.
+__device__ __forceinline__ void best2_insert(float dist, int32_t id, float &b, float &sc,
+                                             int32_t &bi) {
+    if (dist < b) {
+        sc = b;
+        b = dist;
+        bi = id;
+    } else if (dist < sc) {
+        sc = dist;
+    }
+}
+
+// (best, second, id) of the 16 lanes of each lane group, combined; ties put
+// the second equal to the best.
+__device__ __forceinline__ void best2_reduce(float &b, float &sc, int32_t &bi) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        const float ob = __shfl_xor(b, off, 64), os = __shfl_xor(sc, off, 64);
+        const int32_t oi = __shfl_xor(bi, off, 64);
+        if (b <= ob) {
+            sc = fminf(sc, ob);
+        } else {
+            sc = fminf(os, b);
+            b = ob;
+            bi = oi;
+        }
+    }
+}
+
+// beta for a point of norm xn (an upper bound): |dist32 - dist64| over every
+// entry, centroid norms at most cmax.  dist32 = fl(|c|^2_32 - 2 x.c_32):
+// |c|^2 rounded once (2^-24 C^2), the centroid's coordinates rounded once and
+// d products and additions in the accumulation (counted twice, in case the
+// matrix core rounds differently from round-to-nearest: 2 (d + 3) 2^-24 |x| C
+// for x.c, times 2), the final subtraction (2^-24 (C^2 + 2 |x| C)); the FP64
+// value's own error is far below.
+__device__ __forceinline__ float label_beta(float xn, float cmax, int d) {
+    const float c = cmax, e = 0x1p-24f;
+    return (e * (2.f * c * c + (4.f * d + 14.f) * xn * c)) * 1.001f + 1e-30f;
+}
+
+template <int S>
+__device__ __forceinline__ void load_points(const float *__restrict__ Z, int d, int64_t p,
+                                            int grp, float *a, float &sq) {
+    sq = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = 4 * s + grp;
+        a[s] = (p >= 0 && k < d) ? Z[p * d + k] : 0.f;
+        sq += a[s] * a[s];
+    }
+    sq += __shfl_xor(sq, 16, 64);
+    sq += __shfl_xor(sq, 32, 64);
+}
+
+// FP32 pass over nblk blocks of 16 entries (fragments F, norms cn, the
+// entries' identities ids, or identity = slot if ids is null): per lane and
+// result slot the best and second distance and the best identity.
+template <int S>
+__device__ __forceinline__ void pass32(const float *a, const float *__restrict__ F,
+                                       const float *__restrict__ cn,
+                                       const int32_t *__restrict__ ids, int64_t nblk, int lane,
+                                       float *b, float *sc, int32_t *bi) {
+    const int col = lane & 15;
+    float bA[S], bB[S], nA, nB;
+    auto load = [&](float *bf, float &nr, int64_t cb) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
+        nr = cn[cb * 16 + col];
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto step = [&](const float *bf, float nrm, int64_t cb) {
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bf[s], acc, 0, 0, 0);
+        const int32_t id = ids ? ids[cb * 16 + col] : (int32_t)(cb * 16 + col);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) best2_insert(nrm - 2.f * acc[r], id, b[r], sc[r], bi[r]);
+    };
+    load(bA, nA, 0);
+    for (int64_t cb = 0; cb < nblk; cb += 2) {
+        load(bB, nB, cb + 1);
+        step(bA, nA, cb);
+        load(bA, nA, cb + 2);
+        step(bB, nB, cb + 1);
+    }
+}
+
+// Old points [0, n_old), 16 per wave, against the packed changed entries.
+template <int Dp>
+__global__ __launch_bounds__(64 * LW) void label_changed_kernel(
+    const float *__restrict__ Z, int64_t n_old, int d, const float *__restrict__ F,
+    const float *__restrict__ cn, const int32_t *__restrict__ ids, int64_t nblk,
+    const uint8_t *__restrict__ chg, float cmax, int32_t *__restrict__ best_id,
+    float *__restrict__ best32, int32_t *__restrict__ redo, int32_t *__restrict__ nredo) {
+    constexpr int S = Dp / 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int64_t p0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
+    if (p0 >= n_old) return;
+    float a[S], sq;
+    load_points<S>(Z, d, p0 + col < n_old ? p0 + col : -1, grp, a, sq);
+    float b[4], sc[4];
+    int32_t bi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        b[r] = sc[r] = __builtin_inff();
+        bi[r] = -1;
+    }
+    pass32<S>(a, F, cn, ids, nblk, lane, b, sc, bi);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) best2_reduce(b[r], sc[r], bi[r]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * grp + r;
+        const float sqi = __shfl(sq, i, 64);
+        const int64_t p = p0 + i;
+        if (col == 0 && p < n_old) {
+            const int32_t bo = best_id[p];
+            const float dold = best32[p];
+            const float tol = 2.f * label_beta(sqrtf(sqi) * 1.0001f, cmax, d);
+            bool decided = false;
+            if (!__builtin_isnan(dold) && bo >= 0 && !chg[bo]) {
+                if (dold <= b[r]) {
+                    decided = b[r] - dold > tol;                       // the old entry stays
+                } else if (fminf(sc[r], dold) - b[r] > tol) {          // a changed entry wins
+                    best_id[p] = bi[r];
+                    best32[p] = b[r];
+                    decided = true;
+                }
+            }
+            if (!decided) redo[atomicAdd(nredo, 1)] = (int32_t)p;
+        }
+    }
+}
+
+// Appends the new points [n_old, n) to the FP32 list.
+__global__ void label_push_kernel(int64_t n_old, int64_t n, int32_t *__restrict__ list,
+                                  int32_t *__restrict__ count) {
+    const int64_t p = n_old + block_index() * blockDim.x + threadIdx.x;
+    if (p < n) list[atomicAdd(count, 1)] = (int32_t)p;
+}
+
+// Points listed in list32[0, *n32), 16 per wave, against every slot in FP32;
+// undecided ones go to list64.
+template <int Dp>
+__global__ __launch_bounds__(64 * LW) void label_full32_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ list32,
+    const int32_t *__restrict__ n32, const float *__restrict__ F, const float *__restrict__ cn,
+    int64_t nblk, float cmax, int32_t *__restrict__ best_id, float *__restrict__ best32,
+    int32_t *__restrict__ list64, int32_t *__restrict__ n64) {
+    constexpr int S = Dp / 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int64_t q0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
+    const int64_t count = *n32;
+    if (q0 >= count) return;
+    const int64_t mine = q0 + col < count ? list32[q0 + col] : -1;
+    float a[S], sq;
+    load_points<S>(Z, d, mine, grp, a, sq);
+    float b[4], sc[4];
+    int32_t bi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        b[r] = sc[r] = __builtin_inff();
+        bi[r] = -1;
+    }
+    pass32<S>(a, F, cn, nullptr, nblk, lane, b, sc, bi);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) best2_reduce(b[r], sc[r], bi[r]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * grp + r;
+        const float sqi = __shfl(sq, i, 64);
+        const int64_t q = q0 + i;
+        if (col == 0 && q < count) {
+            const int32_t p = list32[q];
+            const float tol = 2.f * label_beta(sqrtf(sqi) * 1.0001f, cmax, d);
+            if (sc[r] - b[r] > tol) {
+                best_id[p] = bi[r];
+                best32[p] = b[r];
+            } else {
+                list64[atomicAdd(n64, 1)] = p;
+            }
+        }
+    }
+}
+
+// Points listed in list64[0, *n64) against every slot in FP64, as the FP64
+// kernel compares them (nearest, first index in leaf order on ties); their
+// FP32 distance is left unknown, so a later update labels them afresh.
+template <int Dp>
+__global__ __launch_bounds__(64 * LW) void label_full64_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ list64,
+    const int32_t *__restrict__ n64, const double *__restrict__ F,
+    const double *__restrict__ cn, const int32_t *__restrict__ idx, int64_t nblk, int64_t nid,
+    int32_t *__restrict__ best_id, float *__restrict__ best32) {
+    constexpr int S = Dp / 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int64_t q0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
+    const int64_t count = *n64;
+    if (q0 >= count) return;
+    const int64_t p = q0 + col < count ? list64[q0 + col] : -1;
+    double a[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = 4 * s + grp;
+        a[s] = (p >= 0 && k < d) ? (double)Z[p * d + k] : 0.0;
+    }
+    double best[4];
+    int32_t bi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        best[r] = __builtin_inf();
+        bi[r] = -1;
+    }
+    for (int64_t cb = 0; cb < nblk; ++cb) {
+        double bf[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
+        const double nrm = cn[cb * 16 + col];
+        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bf[s], acc, 0, 0, 0);
+        const int32_t c = (int32_t)(cb * 16 + col);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double dist = nrm - 2.0 * acc[r];
+            if (dist < best[r] ||
+                (dist == best[r] && bi[r] >= 0 && c < nid && idx[c] < idx[bi[r]])) {
+                best[r] = dist;
+                bi[r] = c;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double v = best[r];
+        int32_t i = bi[r];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const double ov = __shfl_xor(v, off, 64);
+            const int32_t oi = __shfl_xor(i, off, 64);
+            if (ov < v || (ov == v && oi >= 0 && (i < 0 || idx[oi] < idx[i]))) {
+                v = ov;
+                i = oi;
+            }
+        }
+        // FP64 result layout: D[i][j] in lane j + 16 (i % 4), slot i / 4
+        const int64_t q = q0 + 4 * r + grp;
+        if (col == 0 && q < count) {
+            const int32_t pt = list64[q];
+            best_id[pt] = i;
+            best32[pt] = __builtin_nanf("");
+        }
+    }
+}
+
+__global__ void label_map_kernel(int64_t n, const int32_t *__restrict__ best_id,
+                                 const int32_t *__restrict__ idx, int32_t *__restrict__ labels) {
+    const int64_t p = block_index() * blockDim.x + threadIdx.x;
+    if (p < n) {
+        const int32_t e = best_id[p];
+        labels[p] = e >= 0 ? idx[e] : -1;   // -1 only for rows with no finite distance
+    }
+}
+
+// The uploaded changed entries (centroid FP64 m x d, norms, identities) into
+// their slots (FP64 and FP32 fragments and norms) and into the packed FP32
+// array (padding of the last blocks: zero coordinates, norm +inf).  One
+// thread per (entry, coordinate), entries padded to whole blocks.
+__global__ void label_scatter_kernel(int64_t m, int64_t m_pad, int d, int S,
+                                     const double *__restrict__ c, const double *__restrict__ nrm,
+                                     const int32_t *__restrict__ ids, double *__restrict__ f64,
+                                     float *__restrict__ f32, double *__restrict__ cn64,
+                                     float *__restrict__ cn32, float *__restrict__ pf,
+                                     float *__restrict__ pcn, int32_t *__restrict__ pid) {
+    const int Dp = 4 * S;
+    const int64_t t = block_index() * blockDim.x + threadIdx.x;
+    if (t >= m_pad * Dp) return;
+    const int64_t q = t / Dp;
+    const int j = (int)(t % Dp);
+    const int64_t pb = q / 16, pcol = q % 16;
+    const int64_t po = (pb * S + j / 4) * 64 + pcol + 16 * (j % 4);
+    if (q >= m) {
+        pf[po] = 0.f;
+        if (j == 0) {
+            pcn[q] = __builtin_inff();
+            pid[q] = 0;
+        }
+        return;
+    }
+    const int64_t id = ids[q], cb = id / 16, ccol = id % 16;
+    const int64_t so = (cb * S + j / 4) * 64 + ccol + 16 * (j % 4);
+    const double v = j < d ? c[q * d + j] : 0.0;
+    f64[so] = v;
+    f32[so] = (float)v;
+    pf[po] = (float)v;
+    if (j == 0) {
+        cn64[id] = nrm[q];
+        cn32[id] = (float)nrm[q];
+        pcn[q] = (float)nrm[q];
+        pid[q] = (int32_t)id;
+    }
+}
+
+template <typename T>
+__global__ void label_fill_kernel(T *__restrict__ p, int64_t n, T v) {
+    const int64_t i = block_index() * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Device copy of b->d-dimensional fragments for nblk slot blocks plus the
+// spare ones: grown (old contents kept, new slots empty) when the tree has
+// more entries than the arrays hold.
+ifgp_status ensure_slots(ifgp_birch_s *b, int64_t nblk, hipStream_t s) {
+    LabelState &L = b->ls;
+    const int Dp = b->Dp, S = Dp / 4;
+    const int64_t need = nblk + LABEL_SPARE;
+    if (need <= L.cap_blk) return IFGP_OK;
+    const int64_t cap = std::max<int64_t>(need, L.cap_blk * 3 / 2 + 64);
+    Buf f32, f64, cn32, cn64;
+    IFGP_TRY(alloc(f32, sizeof(float) * cap * S * 64, s));
+    IFGP_TRY(alloc(f64, sizeof(double) * cap * S * 64, s));
+    IFGP_TRY(alloc(cn32, sizeof(float) * cap * 16, s));
+    IFGP_TRY(alloc(cn64, sizeof(double) * cap * 16, s));
+    const int64_t old = L.cap_blk;
+    if (old > 0) {
+        IFGP_HIP(hipMemcpyAsync(f32.p, L.f32.p, sizeof(float) * old * S * 64, hipMemcpyDeviceToDevice, s));
+        IFGP_HIP(hipMemcpyAsync(f64.p, L.f64.p, sizeof(double) * old * S * 64, hipMemcpyDeviceToDevice, s));
+        IFGP_HIP(hipMemcpyAsync(cn32.p, L.cn32.p, sizeof(float) * old * 16, hipMemcpyDeviceToDevice, s));
+        IFGP_HIP(hipMemcpyAsync(cn64.p, L.cn64.p, sizeof(double) * old * 16, hipMemcpyDeviceToDevice, s));
+    }
+    const int64_t nf = (cap - old) * S * 64, nc = (cap - old) * 16;
+    label_fill_kernel<float><<<grid_for(ceil_div(nf, 256)), 256, 0, s>>>(f32.as<float>() + old * S * 64, nf, 0.f);
+    label_fill_kernel<double><<<grid_for(ceil_div(nf, 256)), 256, 0, s>>>(f64.as<double>() + old * S * 64, nf, 0.0);
+    label_fill_kernel<float><<<grid_for(ceil_div(nc, 256)), 256, 0, s>>>(cn32.as<float>() + old * 16, nc, __builtin_inff());
+    label_fill_kernel<double><<<grid_for(ceil_div(nc, 256)), 256, 0, s>>>(cn64.as<double>() + old * 16, nc, __builtin_inf());
+    IFGP_LAUNCHED();
+    L.f32 = std::move(f32);
+    L.f64 = std::move(f64);
+    L.cn32 = std::move(cn32);
+    L.cn64 = std::move(cn64);
+    L.cap_blk = cap;
+    return IFGP_OK;
+}
+
+// Host walk of the leaves: identities -> leaf-order indices, the largest
+// centroid norm, and the entries to upload (all of them if the slots are not
+// filled yet, else those changed since the last update), staged in pinned
+// memory and copied to the device, then scattered into place.
+ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, int64_t *m_out, double *cmax) {
+    LabelState &L = b->ls;
+    const int d = b->d, Dp = b->Dp, S = Dp / 4;
+    const int64_t nid = b->next_id;
+    const bool all = !L.slots_valid;
+    const int64_t m = all ? nid : (int64_t)b->chg_list.size();
+    const int64_t m_pad = (ceil_div(m, (int64_t)16) + LABEL_SPARE) * 16;
+    // staging layout: idx (nid int32), chg (nid bytes, padded to 8), centroids
+    // (m x d doubles), norms (m doubles), identities (m int32)
+    const size_t o_chg = sizeof(int32_t) * (size_t)nid;
+    const size_t o_c = (o_chg + (size_t)nid + 7) / 8 * 8;
+    const size_t o_n = o_c + sizeof(double) * (size_t)m * d;
+    const size_t o_id = o_n + sizeof(double) * (size_t)m;
+    const size_t bytes = o_id + sizeof(int32_t) * (size_t)m + 8;
+    if (L.stage_bytes < bytes) {
+        if (L.stage) IFGP_HIP(hipHostFree(L.stage));
+        L.stage = nullptr;
+        L.stage_bytes = 0;
+        const size_t cap = bytes + bytes / 2;
+        IFGP_HIP(hipHostMalloc(&L.stage, cap, 0));
+        L.stage_bytes = cap;
+    }
+    char *h = static_cast<char *>(L.stage);
+    int32_t *idx = reinterpret_cast<int32_t *>(h);
+    uint8_t *chg = reinterpret_cast<uint8_t *>(h + o_chg);
+    double *c = reinterpret_cast<double *>(h + o_c), *nrm = reinterpret_cast<double *>(h + o_n);
+    int32_t *ids = reinterpret_cast<int32_t *>(h + o_id);
+    double mx = 0.0;
+    int64_t k = 0, q = 0;
+    for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
+        for (int e = 0; e < l->size(); ++e, ++k) {
+            const int32_t id = l->id[e];
+            idx[id] = (int32_t)k;
+            mx = std::max(mx, l->cn[e]);
+            if (all) {
+                ids[id] = id;
+                std::memcpy(c + (size_t)id * d, &l->c[(size_t)e * d], sizeof(double) * d);
+                nrm[id] = l->cn[e];
+            }
+        }
+    if (!all)
+        for (int32_t id : b->chg_list) ids[q++] = id;
+    for (int64_t i = 0; i < nid; ++i) chg[i] = all ? 1 : b->chg[(size_t)i];
+    if (!all) {
+        // centroids of the changed entries: find each by a second walk
+        std::vector<int32_t> pos((size_t)nid, -1);
+        for (int64_t i = 0; i < m; ++i) pos[(size_t)ids[i]] = (int32_t)i;
+        for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
+            for (int e = 0; e < l->size(); ++e) {
+                const int32_t at = pos[(size_t)l->id[e]];
+                if (at >= 0) {
+                    std::memcpy(c + (size_t)at * d, &l->c[(size_t)e * d], sizeof(double) * d);
+                    nrm[at] = l->cn[e];
+                }
+            }
+    }
+    for (int32_t id : b->chg_list) b->chg[(size_t)id] = 0;
+    b->chg_list.clear();
+    IFGP_TRY(ensure_slots(b, ceil_div(nid, (int64_t)16), s));
+    IFGP_TRY(ensure(L.raw, bytes, s));
+    IFGP_TRY(ensure(L.idx, sizeof(int32_t) * (size_t)nid, s));
+    IFGP_TRY(ensure(L.chg, (size_t)nid, s));
+    const size_t cmp_bytes = (sizeof(float) * Dp + sizeof(float) + sizeof(int32_t)) * (size_t)m_pad;
+    IFGP_TRY(ensure(L.cmp, cmp_bytes, s));
+    L.cmp_blk = m_pad / 16;
+    IFGP_HIP(hipMemcpyAsync(L.raw.p, h, bytes, hipMemcpyHostToDevice, s));
+    const char *r = static_cast<const char *>(L.raw.p);
+    IFGP_HIP(hipMemcpyAsync(L.idx.p, r, sizeof(int32_t) * (size_t)nid, hipMemcpyDeviceToDevice, s));
+    IFGP_HIP(hipMemcpyAsync(L.chg.p, r + o_chg, (size_t)nid, hipMemcpyDeviceToDevice, s));
+    float *pf = L.cmp.as<float>();
+    float *pcn = pf + (size_t)m_pad * Dp;
+    int32_t *pid = reinterpret_cast<int32_t *>(pcn + m_pad);
+    label_scatter_kernel<<<grid_for(ceil_div(m_pad * Dp, 256)), 256, 0, s>>>(
+        m, m_pad, d, S, reinterpret_cast<const double *>(r + o_c),
+        reinterpret_cast<const double *>(r + o_n), reinterpret_cast<const int32_t *>(r + o_id),
+        L.f64.as<double>(), L.f32.as<float>(), L.cn64.as<double>(), L.cn32.as<float>(), pf, pcn,
+        pid);
+    IFGP_LAUNCHED();
+    // the staging memory is reused by the next update: wait for the copy
+    IFGP_HIP(hipStreamSynchronize(s));
+    L.slots_valid = true;
+    *m_out = m;
+    *cmax = std::sqrt(mx);
     return IFGP_OK;
 }
 
@@ -623,6 +1150,108 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
     }
 #undef IFGP_LABEL
     IFGP_LAUNCHED();
+    return IFGP_OK;
+}
+
+IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, int64_t n,
+                                               int32_t *labels, void *hip_stream) {
+    if (!b || n < 0 || (n > 0 && (!Z || !labels))) {
+        set_error("ifgp_birch_predict_update: need a tree, n >= 0, Z and labels");
+        return IFGP_E_INVALID;
+    }
+    if (b->clusters == 0 || b->broken) {
+        set_error(b->broken ? "ifgp_birch_predict_update: an earlier call ran out of host memory"
+                            : "ifgp_birch_predict_update: the tree holds no points");
+        return IFGP_E_STATE;
+    }
+    if (padded_dim(b->d) > 64) {
+        set_error("ifgp_birch_predict_update: device labelling supports d <= 64");
+        return IFGP_E_INVALID;
+    }
+    if (n > INT32_MAX) {
+        set_error("ifgp_birch_predict_update: n must be below 2^31");
+        return IFGP_E_INVALID;
+    }
+    if (n == 0) return IFGP_OK;
+    int dev = 0;
+    IFGP_HIP(hipGetDevice(&dev));
+    if (b->device != dev) {  // the device copies belong to one device
+        b->centers.reset();
+        b->ls.reset();
+        b->device = dev;
+        b->dirty = true;
+    }
+    const hipStream_t s = (hipStream_t)hip_stream;
+    LabelState &L = b->ls;
+    b->Dp = padded_dim(b->d);
+    const int d = b->d, Dp = b->Dp;
+    if (n < L.n_prev) L.n_prev = 0;  // not the rows labelled before: start over
+    const int64_t n_old = L.n_prev;
+    int64_t m = 0;
+    double cmax = 0.0;
+    try {
+        IFGP_TRY(upload_changes(b, s, &m, &cmax));
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return IFGP_E_OOM;
+    }
+    if (n > L.cap_pts) {
+        const int64_t cap = std::max<int64_t>(n, L.cap_pts * 3 / 2);
+        Buf bid, b32;
+        IFGP_TRY(alloc(bid, sizeof(int32_t) * cap, s));
+        IFGP_TRY(alloc(b32, sizeof(float) * cap, s));
+        if (n_old > 0) {
+            IFGP_HIP(hipMemcpyAsync(bid.p, L.best_id.p, sizeof(int32_t) * n_old, hipMemcpyDeviceToDevice, s));
+            IFGP_HIP(hipMemcpyAsync(b32.p, L.best32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
+        }
+        IFGP_TRY(alloc(L.lists, sizeof(int32_t) * 2 * cap, s));
+        L.best_id = std::move(bid);
+        L.best32 = std::move(b32);
+        L.cap_pts = cap;
+    }
+    IFGP_TRY(ensure(L.counters, sizeof(int32_t) * 2, s));
+    int32_t *cnt = L.counters.as<int32_t>();
+    int32_t *list32 = L.lists.as<int32_t>(), *list64 = list32 + L.cap_pts;
+    label_fill_kernel<int32_t><<<1, 64, 0, s>>>(cnt, 2, 0);
+    IFGP_LAUNCHED();
+    // nearest entry in FP32 within 2 beta of the FP64 one: cmax bounds every |c|
+    const float cm = (float)(cmax * (1.0 + 1e-6)) + 1e-30f;
+    const int64_t nblk = ceil_div((int64_t)b->next_id, (int64_t)16);
+    const float *pf = L.cmp.as<float>();
+    const float *pcn = pf + (size_t)L.cmp_blk * 16 * Dp;
+    const int32_t *pid = reinterpret_cast<const int32_t *>(pcn + L.cmp_blk * 16);
+    const int64_t cblk = ceil_div(m, (int64_t)16);
+    const unsigned wavegrid_old = (unsigned)ceil_div(n_old, (int64_t)16 * LW);
+    const dim3 wavegrid = grid_for(ceil_div(n, (int64_t)16 * LW));
+#define IFGP_UPD(DP)                                                                              \
+    do {                                                                                          \
+        if (n_old > 0)                                                                            \
+            label_changed_kernel<DP><<<grid_for(wavegrid_old), 64 * LW, 0, s>>>(                  \
+                Z, n_old, d, pf, pcn, pid, cblk, L.chg.as<uint8_t>(), cm, L.best_id.as<int32_t>(), \
+                L.best32.as<float>(), list32, cnt);                                               \
+        if (n > n_old)                                                                            \
+            label_push_kernel<<<grid_for(ceil_div(n - n_old, (int64_t)256)), 256, 0, s>>>(        \
+                n_old, n, list32, cnt);                                                           \
+        label_full32_kernel<DP><<<wavegrid, 64 * LW, 0, s>>>(                                     \
+            Z, d, list32, cnt, L.f32.as<float>(), L.cn32.as<float>(), nblk, cm,                   \
+            L.best_id.as<int32_t>(), L.best32.as<float>(), list64, cnt + 1);                      \
+        label_full64_kernel<DP><<<wavegrid, 64 * LW, 0, s>>>(                                     \
+            Z, d, list64, cnt + 1, L.f64.as<double>(), L.cn64.as<double>(), L.idx.as<int32_t>(),  \
+            nblk, (int64_t)b->next_id, L.best_id.as<int32_t>(), L.best32.as<float>());            \
+    } while (0)
+    switch (Dp) {
+    case 8: IFGP_UPD(8); break;
+    case 16: IFGP_UPD(16); break;
+    case 32: IFGP_UPD(32); break;
+    case 64: IFGP_UPD(64); break;
+    default: break;
+    }
+#undef IFGP_UPD
+    IFGP_LAUNCHED();
+    label_map_kernel<<<grid_for(ceil_div(n, (int64_t)256)), 256, 0, s>>>(
+        n, L.best_id.as<int32_t>(), L.idx.as<int32_t>(), labels);
+    IFGP_LAUNCHED();
+    L.n_prev = n;
     return IFGP_OK;
 }
 

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 
@@ -140,9 +141,12 @@ template <> __device__ __forceinline__ uint4 pack<f16_t>(const float *f, float *
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// An FP64 value in a storage type: FP32 and FP16 are rounded once, straight
+// from FP64 (to nearest, ties to even); BF16 through FP32 (two roundings).
 template <typename T> __device__ __forceinline__ T cvt_from_f64(double v) {
     return from_f32<T>((float)v);
 }
+template <> __device__ __forceinline__ f16_t cvt_from_f64<f16_t>(double v) { return (f16_t)v; }
 
 // ---------------------------------------------------------------- Philox / Box-Muller
 // Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit multiply-adds
@@ -834,8 +838,13 @@ FinArgs make_fin_args(ifgp_graph_s *h) {
 // result is the same alone and in any batch.
 constexpr int64_t DEEP_MAX_BYTES = (int64_t)32 << 20;
 constexpr int64_t SHALLOW_MIN_BYTES = (int64_t)224 << 20;
+// A depth forced by ifgp_debug_hop_depth (-1: chosen per graph as below).
+std::atomic<int> g_forced_depth{-1};
+
 int hop_depth(const GraphData &g, int Dp, int storage) {
     if (dtype_bytes(storage) != 2) return DEPTH_NORMAL;
+    const int forced = g_forced_depth.load(std::memory_order_relaxed);
+    if (forced >= 0) return forced;
     const int64_t bytes = g.N * (int64_t)Dp * 2;
     if (Dp >= 64 && bytes >= SHALLOW_MIN_BYTES) return DEPTH_SHALLOW;
     if (bytes <= DEEP_MAX_BYTES) return DEPTH_DEEP;
@@ -1088,6 +1097,8 @@ constexpr int64_t OVERLAP_MIN_NODES = 65536;
 }  // namespace
 
 ifgp_status ensure_side_stream(ifgp_graph_s *h) { return ensure_aux(h); }
+
+int force_hop_depth(int depth) { return g_forced_depth.exchange(depth); }
 
 ifgp_status ensure_scales(ifgp_graph_s *h, double tau, double eps, hipStream_t s) {
     if (scales_cached(h, tau, eps)) return IFGP_OK;

@@ -158,6 +158,9 @@ ifgp_status job_begin_noalloc(ifgp_graph_s *h, double tau, int32_t K, int32_t d,
 // Advance every listed job by one hop (one launch per storage/width class).
 ifgp_status jobs_step(ifgp_graph_s **hs, int n, hipStream_t s);
 int64_t hop_blocks(const GraphData &g, int Dp, int storage);
+// Force the gather depth of every later 2-byte-storage hop (0 normal, 1
+// shallow, 2 deep; -1 = per graph); returns the previous setting.
+int force_hop_depth(int depth);
 int light_rows(const GraphData &g, int Dp, int storage);
 ifgp_status gaussian_input_device(int64_t N, int32_t d, uint64_t seed, int32_t dtype, void *out,
                                   hipStream_t s);

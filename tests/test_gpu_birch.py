@@ -162,3 +162,82 @@ def test_streaming_gp_algorithm2(ifgp):
         assert abs(n_g - n_o) <= 0.01
     G.destroy()
     b.destroy()
+
+
+def _steps(ifgp, X, cuts, thr, B, check_every=True):
+    """Algorithm 2's labelling pattern: rows arrive in batches, the tree is
+    partially fitted to each batch, then every row so far is labelled by the
+    update path and by the full FP64 kernel, which must agree exactly."""
+    import torch
+    Zt = torch.as_tensor(X, device="cuda")
+    b = ifgp.Birch(X.shape[1], thr, B)
+    out = torch.empty(X.shape[0], dtype=torch.int32, device="cuda")
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        b.partial_fit(Zt[lo:hi])
+        upd = b.predict_update(Zt[:hi], out=out[:hi]).cpu().numpy()
+        full = b.predict(Zt[:hi]).cpu().numpy()
+        n_diff = int((upd != full).sum())
+        log(f"  rows {hi}, clusters {b.info()['clusters']}: {n_diff} labels differ")
+        assert n_diff == 0, np.flatnonzero(upd != full)[:10]
+    b.destroy()
+
+
+@pytest.mark.parametrize("n,d,k,thr,B,steps", [(20000, 32, 60, 0.35, 50, 6),
+                                               (9000, 8, 25, 0.15, 20, 5),
+                                               (6000, 64, 30, 0.6, 50, 4),
+                                               (5000, 16, 20, 0.25, 7, 8)])
+def test_label_update_equals_full_labelling(ifgp, n, d, k, thr, B, steps):
+    rng = np.random.default_rng(n + d)
+    c = rng.random((k, d))
+    X = (c[rng.integers(0, k, size=n)] + rng.normal(size=(n, d)) * 0.05).astype(np.float32)
+    log(f"label update: n={n} d={d} threshold={thr} B={B}")
+    _steps(ifgp, X, [n * t // steps for t in range(steps + 1)], thr, B)
+
+
+def test_label_update_exact_ties(ifgp):
+    """Rows equidistant from two centroids (mirror images): FP32 cannot
+    separate them, so the FP64 rule decides (first entry in leaf order), and
+    later updates of those rows stay exact."""
+    d = 8
+    rng = np.random.default_rng(1)
+    left = np.zeros((40, d), np.float32)
+    left[:, 0] = -1.0
+    right = -left
+    mid = np.zeros((300, d), np.float32)
+    mid[:, 1:] = rng.random((300, d - 1)).astype(np.float32)      # x_0 = 0: a tie
+    more = (rng.random((500, d)) * 2 - 1).astype(np.float32)
+    X = np.concatenate([left, right, mid, more])
+    _steps(ifgp, X, [0, 80, 380, 600, 880], 0.05, 10)
+
+
+def test_label_update_on_ffp_embedding_snowball(ifgp):
+    """The Algorithm 2 snowball on a 20k-node graph's BF16 embedding (d = 32,
+    threshold 0.5): at every step the update path's labels equal the full
+    FP64 labelling's."""
+    import torch
+    g = dcsbm(20_000, 25, mean_deg=20.0, ratio=2.5, seed=4)
+    G = ifgp.Graph(g.src, g.dst, g.N)
+    Z = G.embed(-1.0, 8, 32, 1, storage="bf16").cpu().numpy()
+    G.destroy()
+    log("label update on the FFP embedding")
+    _steps(ifgp, Z, [2000 * t for t in range(11)], 0.5, 50)
+
+
+def test_label_update_restart_and_errors(ifgp):
+    import torch
+    rng = np.random.default_rng(2)
+    X = rng.random((3000, 16)).astype(np.float32)
+    Zt = torch.as_tensor(X, device="cuda")
+    b = ifgp.Birch(16, 0.3, 20)
+    with pytest.raises(ifgp.IfgpError):
+        b.predict_update(Zt)                       # no clusters yet
+    b.partial_fit(Zt[:2000])
+    a = b.predict_update(Zt[:2000]).cpu().numpy()
+    b.partial_fit(Zt[2000:])
+    c = b.predict_update(Zt[:1000]).cpu().numpy()  # fewer rows: starts over
+    assert np.array_equal(c, b.predict(Zt[:1000]).cpu().numpy())
+    e = b.predict_update(Zt).cpu().numpy()
+    assert np.array_equal(e, b.predict(Zt).cpu().numpy())
+    assert a.shape == (2000,)
+    b.destroy()
+    assert ifgp.lib.ifgp_birch_predict_update(None, None, 0, None, None) == ifgp.E_INVALID

@@ -202,3 +202,21 @@ def gaussian_features(N: int, d: int, seed: int) -> np.ndarray:
     from its counter-based generator."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((N, d)) / np.sqrt(d)
+
+
+def with_hubs(g: Graph, hubs=(9000, 5000), medium=60, seed: int = 105):
+    """`g` plus star edges that give the hop kernel's row classes rows to
+    work on: node N-1-k joined to hubs[k] random other nodes (hub rows), and
+    `medium` random nodes joined to 150, 158, 166, ... random nodes each
+    (medium rows; some pairs may repeat, which the build merges)."""
+    rng = np.random.default_rng(seed)
+    N = g.N
+    srcs, dsts = [g.src], [g.dst]
+    for k, size in enumerate(hubs):
+        srcs.append(np.full(size, N - 1 - k, dtype=np.int64))
+        dsts.append(rng.choice(N - len(hubs), size=size, replace=False).astype(np.int64))
+    for i, m in enumerate(rng.choice(N - len(hubs), size=medium, replace=False)):
+        size = 150 + 8 * i
+        srcs.append(np.full(size, m, dtype=np.int64))
+        dsts.append(rng.integers(0, N, size=size, dtype=np.int64))
+    return np.concatenate(srcs), np.concatenate(dsts)
