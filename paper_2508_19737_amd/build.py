@@ -34,9 +34,18 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, objdir: str = OBJDIR, defines=()) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# built as usual): each flag applies to the host pass only.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all",
+            "-Xarch_host", "-g"]
+LIB_SAN = os.path.join(HERE, "libifgp_san.so")
+
+
+def _compile(src: str, objdir: str = OBJDIR, defines=(), extra=()) -> str:
     obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *extra, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -48,17 +57,23 @@ def _compile(src: str, objdir: str = OBJDIR, defines=()) -> str:
     return obj
 
 
-def build(jobs: int | None = None, out: str = LIB, defines=()) -> str:
+def build(jobs: int | None = None, out: str = LIB, defines=(), sanitize: bool = False) -> str:
     """Compile and link; `defines` (NAME=VALUE) override the kernels' tuning
     constants (IFGP_HOP_UNROLL, IFGP_LIGHT_ROWS, IFGP_MED_DEGREE,
-    IFGP_HUB_DEGREE)."""
-    objdir = OBJDIR if out == LIB else os.path.join(OBJDIR, "variant_" + str(abs(hash(out))))
+    IFGP_HUB_DEGREE).  sanitize=True builds the host code with ASan and
+    UBSan (load it with the clang ASan runtime preloaded; see
+    sanitize_check.py)."""
+    extra = SANITIZE if sanitize else []
+    objdir = OBJDIR if out == LIB and not sanitize else os.path.join(
+        OBJDIR, "variant_" + ("san" if sanitize else str(abs(hash(out)))))
     os.makedirs(objdir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, objdir, defines), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, objdir, defines, extra), SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    link_extra = (["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                   "-shared-libsan"] if sanitize else [])
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
@@ -71,5 +86,10 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--out", default=LIB)
     ap.add_argument("--define", action="append", default=[])
+    ap.add_argument("--sanitize", action="store_true",
+                    help="host code with ASan + UBSan, written to libifgp_san.so")
     a = ap.parse_args()
-    print(build(a.jobs, os.path.abspath(a.out), a.define))
+    if a.sanitize:
+        print(build(a.jobs, LIB_SAN, a.define, sanitize=True))
+    else:
+        print(build(a.jobs, os.path.abspath(a.out), a.define))

@@ -1,0 +1,49 @@
+"""Run tests against the host-sanitized build of libifgp: the library's host
+code (argument checks, handle lifecycle, staging, the caching allocator, the
+BIRCH CF-tree) compiled with AddressSanitizer and UndefinedBehaviorSanitizer,
+device code as usual.
+
+    python paper_2508_19737_amd/sanitize_check.py [--no-build] [pytest args]
+
+Default pytest arguments: -x -q -m "not gpu" tests/.  The clang ASan runtime is
+preloaded (Python itself is not instrumented), leak detection is off (the
+interpreter keeps its allocations until exit) and any report stops the run
+with a non-zero status.
+"""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def asan_runtime() -> str:
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise SystemExit("clang ASan runtime not found under /opt/rocm/lib/llvm")
+    return hits[-1]
+
+
+def main(argv):
+    build = "--no-build" not in argv
+    args = [a for a in argv if a != "--no-build"] or ["-x", "-q", "-m", "not gpu", "tests/"]
+    sys.path.insert(0, HERE)
+    import build as b
+    if build:
+        b.build(out=b.LIB_SAN, sanitize=True)
+    nm = subprocess.run(["nm", "-D", b.LIB_SAN], capture_output=True, text=True).stdout
+    if "__asan_report" not in nm or "__ubsan_handle" not in nm:
+        raise SystemExit(f"{b.LIB_SAN} is not instrumented")
+    env = dict(os.environ, IFGP_LIBRARY=b.LIB_SAN, LD_PRELOAD=asan_runtime(),
+               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    print(f"sanitizer run: IFGP_LIBRARY={b.LIB_SAN}", flush=True)
+    return subprocess.call([sys.executable, "-m", "pytest", *args], cwd=ROOT, env=env)
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
