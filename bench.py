@@ -328,7 +328,10 @@ def bench_serving(a, say):
     from paper_2508_19737_amd import serve
     from workloads.serving import graph_pool, request_stream
     say(f"serving: pool of {a.serve_pool} graphs, {a.serve_requests} requests")
-    pool = graph_pool(pool=a.serve_pool, n_min=1000, n_max=500_000, seed=3)
+    t_gen = time.perf_counter()
+    pool = graph_pool(pool=a.serve_pool, n_min=1000, n_max=500_000, seed=3,
+                      cache_dir=os.path.join(ROOT, "build", "serving_pool"))
+    say(f"serving: pool ready in {time.perf_counter() - t_gen:.1f} s")
 
     def reqs(rate, storage, n):
         return [serve.Request(rid=i, arrival=x["arrival"], src=x["graph"].src, dst=x["graph"].dst,
@@ -353,10 +356,16 @@ def bench_serving(a, say):
     seq = serve.summarize(serve.sequential(reqs(rate, "f32", n), keep_outputs=False))
     say(f"serving: one at a time {seq}")
     closed_s = serve.summarize(serve.sequential(reqs(float("inf"), "f32", n), keep_outputs=False))
-    sizes = [g.N for g in pool]
+    sizes = np.array([g.N for g in pool])
+    used = np.array([g.N for g in {id(x["graph"]): x["graph"]
+                                   for x in request_stream(pool, n, rate, seed=3)}.values()])
     return {"workload": f"{n} requests, Poisson rate {rate:.1f}/s (0.7 x FP32 one-at-a-time "
                         f"capacity), graphs from a seeded pool of {len(pool)} DC-SBM graphs with "
-                        f"N {min(sizes)}..{max(sizes)}, d in {{32,64}}, tau=-1, K=8",
+                        f"N {sizes.min()}..{sizes.max()}, d in {{32,64}}, tau=-1, K=8",
+            "pool_size": int(len(pool)), "pool_graphs_requested": int(used.size),
+            "pool_N_quantiles": {q: int(np.percentile(sizes, p)) for q, p in
+                                 (("min", 0), ("p10", 10), ("p50", 50), ("p90", 90), ("max", 100))},
+            "pool_nnz_total": int(sum(2 * g.num_edges for g in pool)),
             "rate_per_s": rate,
             "batched_bf16": batched, "one_at_a_time_fp32": seq,
             "closed_loop_batched_bf16": closed_b, "closed_loop_one_at_a_time_fp32": closed_s}
@@ -380,8 +389,9 @@ def main():
     ap.add_argument("--no-snowball", action="store_true")
     ap.add_argument("--no-paper-settings", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-storage-legs", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reads 1 GiB, writes 1 GiB) so "
                          "that profiler byte counters can be scaled against known traffic")
@@ -464,6 +474,52 @@ def main():
     bytes_hop = hop_bytes(a.N, nnz, Dp, b, blocks)
     achieved = bytes_hop / (hop_ms_avg * 1e-3) / 1e9
     comp = hop_bytes_compulsory(a.N, nnz, Dp, b, blocks) / (hop_ms_avg * 1e-3) / 1e9
+    traffic = measured_traffic((a.N, a.d, a.K, a.storage, a.blocks) ==
+                               (2_000_000, 64, 8, "bf16", 200))
+
+    # the same graph with the other storage types: step (build + embed),
+    # embed alone and the hop kernel, on the same no-reuse byte model
+    legs = {}
+    if not a.no_storage_legs:
+        for st in ("bf16", "f16", "f32"):
+            if st == a.storage:
+                continue
+            say(f"storage leg {st}")
+            kst = dict(storage=st)
+            for _ in range(2):
+                Gx = ifgp.Graph(src, dst, a.N)
+                Gx.embed(a.tau, a.K, a.d, 1, out=out, **kst)
+                Gx.destroy()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                Gx = ifgp.Graph(src, dst, a.N)
+                Gx.embed(a.tau, a.K, a.d, 1, out=out, **kst)
+                Gx.destroy()
+            torch.cuda.synchronize()
+            leg_step = (time.perf_counter() - t0) / a.steps
+            G.embed(a.tau, a.K, a.d, 1, out=out, **kst)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                G.embed(a.tau, a.K, a.d, 1, out=out, **kst)
+            torch.cuda.synchronize()
+            leg_embed = (time.perf_counter() - t0) / a.steps
+            G.timing(True)
+            for _ in range(a.steps):
+                G.embed(a.tau, a.K, a.d, 1, out=out, **kst)
+            torch.cuda.synchronize()
+            nh, hm = G.timing_read()
+            G.timing(False)
+            hm /= max(nh, 1)
+            bst = {"bf16": 2, "f16": 2, "f32": 4}[st]
+            bh = hop_bytes(a.N, nnz, Dp, bst, blocks)
+            legs[st] = {"step_ms": leg_step * 1e3, "value": nnz * a.d * a.K / leg_step,
+                        "embed_ms": leg_embed * 1e3, "embed_value": nnz * a.d * a.K / leg_embed,
+                        "hop_ms": hm, "hop_bytes_per_launch": bh,
+                        "hop_achieved_gbs": bh / (hm * 1e-3) / 1e9,
+                        "hop_frac": bh / (hm * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            say(f"  {st}: step {leg_step*1e3:.3f} ms, embed {leg_embed*1e3:.3f} ms, hop {hm:.4f} ms")
 
     cpu = cpu_par = None
     if not a.no_cpu_baseline:
@@ -497,18 +553,23 @@ def main():
         "dtype": a.storage,
         "data": "synthetic",
         "config": {"workload": f"DC-SBM N={a.N} nnz={nnz} d={a.d} tau={a.tau} K={a.K} "
-                               f"{a.storage} storage; step = build graph + embed",
+                               f"{a.storage} storage; step = graph build from a device-resident "
+                               f"edge list + embed (value counts the build; embed_only excludes it)",
                    "N": a.N, "nnz": nnz, "d": a.d, "K": a.K, "tau": a.tau,
                    "storage": a.storage, "global_batch": 1, "parallelism": "none"},
         "embed_only": {"ms": t_embed * 1e3, "value": work / t_embed,
                        "build_ms": (t_step - t_embed) * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic((a.N, a.d, a.K, a.storage, a.blocks) ==
-                                                 (2_000_000, 64, 8, "bf16", 200)),
+                     "traffic": traffic,
                      "kernel": "hop_kernel", "bytes_per_launch": bytes_hop,
                      "launch_ms": hop_ms_avg, "model": "no gathered row reused from cache",
-                     "achieved_compulsory": comp},
+                     "achieved_compulsory": comp,
+                     # HBM-side bytes the counters saw per launch, over the same launch time
+                     "traffic_achieved": None if traffic is None else traffic / (hop_ms_avg * 1e-3) / 1e9,
+                     "traffic_frac": None if traffic is None
+                     else traffic / (hop_ms_avg * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "storage_legs": legs,
         "cpu_baseline": cpu,
         "cpu_baseline_parallel": cpu_par,
         "streaming": streaming,

@@ -5,16 +5,20 @@ type) arriving over time, as in the paper's streaming setting (Sec. II,
 Algorithm 2) generalised to a stream of independent graphs.  The loop
 
   * admits waiting requests in arrival order while a slot is free and the
-    request's resident HBM footprint fits the memory budget (a request that
-    does not fit waits; nothing is rejected for lack of room unless it could
-    never fit);
+    request's HBM footprint fits the memory budget: while its graph is being
+    built, the resident footprint plus the build's transient buffers; once
+    built, the resident footprint alone (a request that does not fit waits;
+    nothing is rejected for lack of room unless it could never fit);
   * builds admitted graphs on a side stream from a worker thread, so graph
     construction overlaps the hops of graphs already running;
   * starts a graph's job at the next hop boundary once its build is done;
   * advances every running job by one hop per iteration, all graphs of one
     (storage, width, gather depth) class in one kernel launch (ifgp_job_step);
   * retires a job when its output is complete on the device, frees its slot
-    and memory, and records its latency (completion - arrival).
+    and memory, and records its latency (completion - arrival);
+  * a request whose build or job start fails (IfgpError, e.g. out of device
+    memory or an id out of range) is recorded as failed with its message, its
+    slot and memory are released, and the loop goes on with the others.
 
 `sequential()` is the plain one-at-a-time path the batched loop is compared
 with: build, embed, synchronise, next.
@@ -52,6 +56,7 @@ class Request:
     t_start: float = float("nan")
     t_done: float = float("nan")
     cancelled: bool = False
+    error: Optional[str] = None     # set if the request failed
 
     @property
     def latency(self) -> float:
@@ -63,6 +68,14 @@ class Request:
         FP32 output."""
         nnz = 2 * int(self.src.shape[0])
         return ifgp.footprint_bytes(self.N, max(nnz, 0), self.d, self.storage) + 4 * self.N * self.d
+
+    def build_transient(self) -> int:
+        """Device bytes a graph build holds on top of the resident graph until
+        it returns, bounded from above: host edges staged on the device (16 per
+        pair), two 64-bit keys per pair and as many for the sort's second
+        buffer (32), a column index per key (8), per-tile digit counts and
+        bucket bounds (under 8), and per-node sort keys and counters (32 N)."""
+        return 64 * int(self.src.shape[0]) + 32 * self.N
 
 
 class Admission:
@@ -106,6 +119,11 @@ class Admission:
             out.append((r, cost))
         return out
 
+    def shrink(self, nbytes: int):
+        """Part of an admitted request's memory is no longer needed (its slot
+        stays taken)."""
+        self.used -= nbytes
+
     def release(self, cost: int):
         self.used -= cost
         self.slots -= 1
@@ -125,6 +143,7 @@ class Server:
         self.main = torch.cuda.current_stream()
         self._tls = threading.local()            # one side stream per build worker
         self.pool = cf.ThreadPoolExecutor(max_workers=max(1, build_workers))
+        self.failed: list = []                   # requests whose build or job start failed
         # Library buffers come from the library's own caching allocator: build
         # worker threads then never call back into Python for memory.
         ifgp.use_hip_allocator()
@@ -184,7 +203,7 @@ class Server:
                 next_report = now + 1.0
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
-                self.adm.offer(r, r.footprint())
+                self.adm.offer(r, r.footprint() + r.build_transient())
             for r, cost in self.adm.admit():
                 r.t_admit = self.clock() - t0
                 building.append((r, cost, self.pool.submit(self._build, r)))
@@ -192,12 +211,21 @@ class Server:
             still = []
             for r, cost, fut in building:
                 if fut.done():
-                    G, ev = fut.result()
-                    self.main.wait_event(ev)
-                    r.out = G.job_begin(r.tau, r.K, r.d, r.seed, stream=self.main, storage=r.storage)
+                    moved = True
+                    transient = r.build_transient()
+                    G = None
+                    try:
+                        G, ev = fut.result()
+                        self.adm.shrink(transient)
+                        cost -= transient
+                        self.main.wait_event(ev)
+                        r.out = G.job_begin(r.tau, r.K, r.d, r.seed, stream=self.main,
+                                            storage=r.storage)
+                    except ifgp.IfgpError as e:
+                        self._fail(r, cost, G, e, t0)
+                        continue
                     r.t_start = self.clock() - t0
                     active.append((r, cost, G))
-                    moved = True
                 else:
                     still.append((r, cost, fut))
             building = still
@@ -240,6 +268,16 @@ class Server:
                     if dt > 0:
                         time.sleep(min(dt, 0.001))
         return done
+
+    def _fail(self, r, cost, G, err, t0):
+        """Record a failed request and give back its slot and memory."""
+        if G is not None:
+            G.destroy()
+        self.adm.release(cost)
+        r.error = str(err)
+        r.out = None
+        r.t_done = self.clock() - t0
+        self.failed.append(r)
 
     def close(self):
         self.pool.shutdown(wait=True)

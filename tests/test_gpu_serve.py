@@ -14,7 +14,9 @@ def make_requests(serve, specs):
                           storage=s["storage"]) for i, s in enumerate(specs)]
 
 
-@pytest.mark.parametrize("max_slots,budget", [(16, None), (1, None), (3, 64 << 20)])
+# 96 MiB: the largest request needs 69 MiB while its graph is built (resident
+# footprint plus the build's transient buffers), so requests queue for memory
+@pytest.mark.parametrize("max_slots,budget", [(16, None), (1, None), (3, 96 << 20)])
 def test_served_equals_alone(max_slots, budget):
     import torch
     import paper_2508_19737_amd as ifgp
@@ -49,4 +51,29 @@ def test_sequential_path_matches_fp32_alone():
     for r in done:
         G = ifgp.Graph(r.src, r.dst, r.N)
         assert torch.equal(r.out, G.embed(r.tau, r.K, r.d, r.seed, storage="f32"))
+        G.destroy()
+
+
+def test_failed_request_is_recorded_and_the_loop_goes_on():
+    """A request whose build fails (a node id out of range, which the build's
+    own check reports as IFGP_E_RANGE) is recorded with its error; its slot and
+    memory come back and every other request is served as alone."""
+    import torch
+    import paper_2508_19737_amd as ifgp
+    from paper_2508_19737_amd import serve
+    pool = graph_pool(pool=4, n_min=1000, n_max=20_000, seed=5, workers=1)
+    reqs = make_requests(serve, request_stream(pool, 8, rate=float("inf"), seed=5))
+    bad = reqs[3]
+    bad.src = bad.src.copy()
+    bad.src[7] = bad.N + 3
+    srv = serve.Server(max_slots=2)
+    done = srv.run(reqs)
+    srv.close()
+    assert [r.rid for r in srv.failed] == [3]
+    assert "range" in srv.failed[0].error.lower() or "[-2]" in srv.failed[0].error
+    assert sorted(r.rid for r in done) == [0, 1, 2, 4, 5, 6, 7]
+    assert srv.adm.used == 0 and srv.adm.slots == 0
+    for r in done:
+        G = ifgp.Graph(r.src, r.dst, r.N)
+        assert torch.equal(r.out, G.embed(r.tau, r.K, r.d, r.seed, storage=r.storage))
         G.destroy()

@@ -52,3 +52,16 @@ def test_bad_limits():
         Admission(0, 10)
     with pytest.raises(ValueError):
         Admission(1, 0)
+
+
+def test_shrink_keeps_the_slot():
+    a = Admission(max_slots=2, budget_bytes=100)
+    a.offer(R(0), 70)            # 40 resident + 30 while building
+    a.offer(R(1), 50)
+    assert [r.rid for r, _ in a.admit()] == [0]
+    a.shrink(30)                 # build done: only the resident part stays
+    assert a.used == 40 and a.slots == 1
+    assert [r.rid for r, _ in a.admit()] == [1]
+    a.release(40)
+    a.release(50)
+    assert a.used == 0 and a.slots == 0
