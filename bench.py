@@ -214,8 +214,11 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
     each with its edges to earlier nodes.  A step merges the new topology
     (ifgp_stream_add with new_N > N), re-embeds the cumulative graph
     (d=32, tau=-1, K=8, BF16), partially fits BIRCH (threshold 0.5) to the
-    new nodes' embeddings, keeps them, and labels every node so far.  Per-step
-    latency with its parts; every input already in device memory."""
+    new nodes' embeddings, keeps them, and labels every node so far
+    (ifgp_birch_predict_update: old rows against the changed centroids only).
+    Per-step latency with its parts, and the full FP64 labelling of the same
+    rows timed beside it (not part of the step); every input already in
+    device memory."""
     import torch
     from workloads import dcsbm
     say("snowball: N=200000, 10 node batches")
@@ -231,6 +234,7 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
     d = 32
     kept = torch.empty((g.N, d), dtype=torch.float32, device="cuda")
     labels = torch.empty(g.N, dtype=torch.int32, device="cuda")
+    full = torch.empty(g.N, dtype=torch.int32, device="cuda")
     rows = []
     for rep in range(reps + 1):
         G, b = None, ifgp.Birch(d, 0.5, 50)
@@ -248,15 +252,21 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
             t1 = time.perf_counter()
             b.partial_fit(kept[n_0:n_t])
             t2 = time.perf_counter()
-            b.predict(kept[:n_t], out=labels[:n_t])
+            b.predict_update(kept[:n_t], out=labels[:n_t])
             torch.cuda.synchronize()
             t3 = time.perf_counter()
+            # beside the pipeline: the same labels recomputed in full (FP64)
+            b.predict(kept[:n_t], out=full[:n_t])
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            same = bool(torch.equal(full[:n_t], labels[:n_t]))
             if rep > 0:
-                rows.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2, b.info()["clusters"]))
+                rows.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2, b.info()["clusters"], t4 - t3,
+                             float(same)))
         G.destroy()
         b.destroy()
-    r = np.array(rows) * np.array([1e3, 1e3, 1e3, 1e3, 1.0])
-    per = r.reshape(reps, steps, 5).mean(axis=0)
+    r = np.array(rows) * np.array([1e3, 1e3, 1e3, 1e3, 1.0, 1e3, 1.0])
+    per = r.reshape(reps, steps, 7).mean(axis=0)
     return {"workload": "Alg. 2 snowball: DC-SBM N=200000 B=100 mean degree 20, nodes arrive in 10 "
                         "batches of 20000 (seeded order) with their edges to earlier nodes; per step "
                         "stream_add(new_N) + FFP d=32 tau=-1 K=8 bf16 + BIRCH partial fit of the new "
@@ -266,7 +276,9 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
             "per_step_mean_ms": {"total": [float(x) for x in per[:, 0]],
                                  "merge_and_embed": [float(x) for x in per[:, 1]],
                                  "birch_partial_fit_host": [float(x) for x in per[:, 2]],
-                                 "labels_device": [float(x) for x in per[:, 3]]},
+                                 "labels_device": [float(x) for x in per[:, 3]],
+                                 "labels_full_fp64_for_comparison": [float(x) for x in per[:, 5]]},
+            "labels_equal_full_fp64": bool(r[:, 6].min() == 1.0),
             "clusters_final": int(per[-1, 4])}
 
 

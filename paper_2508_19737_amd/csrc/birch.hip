@@ -590,9 +590,12 @@ __device__ __forceinline__ void best2_reduce(float &b, float &sc, int32_t &bi) {
 // matrix core rounds differently from round-to-nearest: 2 (d + 3) 2^-24 |x| C
 // for x.c, times 2), the final subtraction (2^-24 (C^2 + 2 |x| C)); the FP64
 // value's own error is far below.
+#ifndef IFGP_LABEL_TOL_SCALE
+#define IFGP_LABEL_TOL_SCALE 1.0f  // > 1 sends more rows to the FP64 pass (never fewer than needed)
+#endif
 __device__ __forceinline__ float label_beta(float xn, float cmax, int d) {
     const float c = cmax, e = 0x1p-24f;
-    return (e * (2.f * c * c + (4.f * d + 14.f) * xn * c)) * 1.001f + 1e-30f;
+    return (e * (2.f * c * c + (4.f * d + 14.f) * xn * c)) * 1.001f * IFGP_LABEL_TOL_SCALE + 1e-30f;
 }
 
 template <int S>
@@ -761,44 +764,47 @@ __global__ __launch_bounds__(64 * LW) void label_full64_kernel(
         const int k = 4 * s + grp;
         a[s] = (p >= 0 && k < d) ? (double)Z[p * d + k] : 0.0;
     }
+    // per result slot: best distance, its entry (identity) and that entry's
+    // leaf-order index, so that (distance, index) is compared in one step
     double best[4];
-    int32_t bi[4];
+    int32_t bi[4], bx[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         best[r] = __builtin_inf();
         bi[r] = -1;
+        bx[r] = INT32_MAX;
     }
     for (int64_t cb = 0; cb < nblk; ++cb) {
         double bf[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
         const double nrm = cn[cb * 16 + col];
+        const int64_t c64 = cb * 16 + col;
+        const int32_t cx = c64 < nid ? idx[c64] : INT32_MAX;  // unused slots sort last
         d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bf[s], acc, 0, 0, 0);
-        const int32_t c = (int32_t)(cb * 16 + col);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double dist = nrm - 2.0 * acc[r];
-            if (dist < best[r] ||
-                (dist == best[r] && bi[r] >= 0 && c < nid && idx[c] < idx[bi[r]])) {
-                best[r] = dist;
-                bi[r] = c;
-            }
+            const bool take = dist < best[r] || (dist == best[r] && cx < bx[r]);
+            best[r] = take ? dist : best[r];
+            bi[r] = take ? (int32_t)c64 : bi[r];
+            bx[r] = take ? cx : bx[r];
         }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         double v = best[r];
-        int32_t i = bi[r];
+        int32_t i = bi[r], x = bx[r];
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) {
             const double ov = __shfl_xor(v, off, 64);
-            const int32_t oi = __shfl_xor(i, off, 64);
-            if (ov < v || (ov == v && oi >= 0 && (i < 0 || idx[oi] < idx[i]))) {
-                v = ov;
-                i = oi;
-            }
+            const int32_t oi = __shfl_xor(i, off, 64), ox = __shfl_xor(x, off, 64);
+            const bool take = ov < v || (ov == v && ox < x);
+            v = take ? ov : v;
+            i = take ? oi : i;
+            x = take ? ox : x;
         }
         // FP64 result layout: D[i][j] in lane j + 16 (i % 4), slot i / 4
         const int64_t q = q0 + 4 * r + grp;

@@ -241,3 +241,32 @@ def test_label_update_restart_and_errors(ifgp):
     assert a.shape == (2000,)
     b.destroy()
     assert ifgp.lib.ifgp_birch_predict_update(None, None, 0, None, None) == ifgp.E_INVALID
+
+
+def test_label_update_ties_within_one_lane(ifgp):
+    """Identical centroids in separate leaf entries (BIRCH leaves them when
+    equal rows are routed to different leaves) give exact distance ties.  On
+    the first 20,000 arriving nodes of the 200k-node snowball graph, 29 rows
+    tie between entries whose identities differ by a multiple of 16, so the
+    FP64 pass compares them in one lane: it must still pick the first entry in
+    leaf order, as the full FP64 labelling does."""
+    import torch
+    g = dcsbm(200_000, 100, mean_deg=20.0, ratio=2.5, seed=0)
+    rank = np.argsort(np.random.default_rng(1).permutation(g.N))
+    src, dst = rank[g.src], rank[g.dst]
+    m = np.maximum(src, dst) < 20_000
+    G = ifgp.Graph(torch.as_tensor(src[m], device="cuda"), torch.as_tensor(dst[m], device="cuda"),
+                   20_000)
+    Z = G.embed(-1.0, 8, 32, 1, storage="bf16")
+    G.destroy()
+    b = ifgp.Birch(32, 0.5, 50).partial_fit(Z)
+    C = b.centers()
+    X = Z.cpu().numpy().astype(np.float64)
+    dist = (C * C).sum(axis=1)[None, :] - 2.0 * X @ C.T
+    n_tied = int(((dist == dist.min(axis=1, keepdims=True)).sum(axis=1) > 1).sum())
+    log(f"rows with an exact tie: {n_tied}")
+    assert n_tied >= 20
+    upd = b.predict_update(Z).cpu().numpy()
+    full = b.predict(Z).cpu().numpy()
+    assert np.array_equal(upd, full), np.flatnonzero(upd != full)[:10]
+    b.destroy()
