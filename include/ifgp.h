@@ -367,18 +367,40 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
  * values and new rows follow them (rows 0 .. m-1 of Z hold what they held in
  * the previous call, m = that call's n <= n; n < m starts over).  The call
  * compares each old row only with the cluster centroids created or changed
- * since the previous call (its nearest entry is otherwise unchanged), unless
- * that row's nearest entry itself changed; distances are taken in FP32 on the
+ * since the previous call (its nearest entry is otherwise unchanged; if that
+ * entry moved, a bound on the row's second-nearest distance kept from before
+ * stands for the unchanged ones); distances are taken in FP32 on the
  * matrix cores with a rigorous bound on their difference from the FP64 ones,
  * and rows whose nearest and second-nearest entries lie within that bound are
- * labelled in FP64 by ifgp_birch_predict's rule (first index on ties).  The
+ * labelled in FP64 by ifgp_birch_predict's rule (first index on ties), over
+ * the entries within twice the bound of the FP32 nearest (up to 8; all
+ * entries for rows with more).
+ * Entries whose centroids and norms are equal bit for bit (twins, which tie
+ * exactly for every row) count once in FP32, and a row nearest to them gets
+ * the first of them in leaf order, as ifgp_birch_predict gives.  The
  * centroids and what is known of each row stay in device memory held by the
- * tree (about 16 bytes per row and 12 Dp per cluster, Dp = d rounded up to
- * 8, 16, 32 or 64).  Z: device, n x d FP32,
- * d <= 64; labels: device int32 n.  Errors as ifgp_birch_predict.
+ * tree (about 24 bytes per row, 12 Dp per cluster, Dp = d rounded up to 8,
+ * 16, 32 or 64, up to 16 bytes per row and entry chunk for a pass's partial
+ * results, and 68 bytes per row left to the FP64 rule).  The call synchronises hip_stream (after the upload of
+ * the changed centroids, and before each pass, whose size it reads back).
+ * Z: device, n x d FP32, d <= 64; labels: device int32 n.  Errors as
+ * ifgp_birch_predict.
  */
 IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, int64_t n,
                                                int32_t *labels, void *hip_stream);
+
+/*
+ * What the last ifgp_birch_predict_update did (host values; any pointer may
+ * be NULL): new_entries = twin groups new since the call before (the entries
+ * old rows were compared with), fp32_rows = rows labelled against every
+ * entry in FP32 (new rows and old ones not settled by that comparison),
+ * fp64_rows = rows of those left to the FP64 rule (ties and near ties),
+ * fp64_full_rows = rows of those with more than 8 candidates, compared in
+ * FP64 with every entry.  IFGP_E_INVALID for a NULL tree.
+ */
+IFGP_API ifgp_status ifgp_birch_update_stats(ifgp_birch_t b, int64_t *new_entries,
+                                             int64_t *fp32_rows, int64_t *fp64_rows,
+                                             int64_t *fp64_full_rows);
 
 /* Release the tree and its device copy (NULL is accepted). */
 IFGP_API ifgp_status ifgp_birch_destroy(ifgp_birch_t b);

@@ -33,7 +33,8 @@ EXPORTS = [
     "ifgp_timing_read", "ifgp_debug_grid_x", "ifgp_debug_hop_depth",
     "ifgp_destroy", "ifgp_last_error", "ifgp_version",
     "ifgp_birch_create", "ifgp_birch_partial_fit", "ifgp_birch_info", "ifgp_birch_centers",
-    "ifgp_birch_predict", "ifgp_birch_predict_update", "ifgp_birch_destroy",
+    "ifgp_birch_predict", "ifgp_birch_predict_update", "ifgp_birch_update_stats",
+    "ifgp_birch_destroy",
 ]
 
 
@@ -88,6 +89,7 @@ def _load():
         "ifgp_birch_centers": [P, P],
         "ifgp_birch_predict": [P, P, i64, P, P],
         "ifgp_birch_predict_update": [P, P, i64, P, P],
+        "ifgp_birch_update_stats": [P, P, P, P, P],
         "ifgp_birch_destroy": [P],
     }
     for name, args in sig.items():
@@ -462,6 +464,14 @@ class Birch:
                                             Zt.shape[0], ctypes.c_void_p(out.data_ptr()),
                                             _stream_ptr(stream)))
         return out
+
+    def update_stats(self):
+        """ifgp_birch_update_stats: {"new_entries", "fp32_rows", "fp64_rows",
+        "fp64_full_rows"} of the last predict_update."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(lib.ifgp_birch_update_stats(self._live(), *[ctypes.byref(x) for x in v]))
+        return dict(new_entries=v[0].value, fp32_rows=v[1].value, fp64_rows=v[2].value,
+                    fp64_full_rows=v[3].value)
 
     def fit_predict(self, Z, stream=None):
         return self.partial_fit(Z, stream).predict(Z, stream=stream)

@@ -11,6 +11,7 @@
 //   device  labelling: every point against every leaf-entry centroid, a
 //           dense N x M x d contraction with an argmin, on the FP64 matrix
 //           cores (the same precision as the tree's own decisions).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -127,40 +128,182 @@ bool use_avx2() {
 
 }  // namespace
 
+// Leaf entries whose centroids and stored norms are equal bit for bit (BIRCH
+// leaves such twins when equal rows descend to different leaves) are at the
+// same distance from every point, in any precision.  They form a twin group:
+// the FP32 passes see one member of each group (its representative; the
+// others have norm +inf there), and a point nearest to a group takes the
+// group's first entry in leaf order, as the FP64 rule does.
+struct TwinGroups {
+    struct Group {
+        uint64_t key = 0;
+        int32_t rep = -1;    // the member the FP32 passes see
+        int32_t fresh = 0;   // members that joined in the current update
+        int32_t size = 0;
+        int32_t head = -1;   // first member; the rest follow through next
+        int32_t mpos = -1;   // position in multi, -1 if fewer than two members
+    };
+    std::vector<Group> g;
+    std::vector<int32_t> spare;            // group numbers free for reuse
+    std::vector<int32_t> of, next, prev;   // per identity: its group (-1 before it joins one)
+                                           // and its neighbours in the group's list
+    std::vector<int32_t> multi;            // groups of two or more members
+    // groups by key: open addressing, linear probing, capacity a power of two
+    // (slot group -1 = empty); keys of different centroids may be equal, so a
+    // lookup compares the centroids too
+    std::vector<uint64_t> hkey;
+    std::vector<int32_t> hgrp;
+    size_t used = 0;
+
+    void clear() {
+        g.clear(); spare.clear(); of.clear(); next.clear(); prev.clear(); multi.clear();
+        hkey.clear(); hgrp.clear();
+        used = 0;
+    }
+    void resize(size_t nid) {
+        of.resize(nid, -1);
+        next.resize(nid, -1);
+        prev.resize(nid, -1);
+    }
+    int32_t make(uint64_t key) {
+        int32_t gi;
+        if (!spare.empty()) {
+            gi = spare.back();
+            spare.pop_back();
+        } else {
+            gi = (int32_t)g.size();
+            g.emplace_back();
+        }
+        g[gi] = Group();
+        g[gi].key = key;
+        insert_key(key, gi);
+        return gi;
+    }
+    void drop(int32_t gi) {
+        erase_key(g[gi].key, gi);
+        g[gi].rep = -1;
+        spare.push_back(gi);
+    }
+    void add(int32_t gi, int32_t id) {
+        Group &G = g[gi];
+        next[id] = G.head;
+        prev[id] = -1;
+        if (G.head >= 0) prev[G.head] = id;
+        G.head = id;
+        of[id] = gi;
+        if (++G.size == 2) {
+            G.mpos = (int32_t)multi.size();
+            multi.push_back(gi);
+        }
+    }
+    void remove(int32_t gi, int32_t id) {
+        Group &G = g[gi];
+        if (prev[id] >= 0) next[prev[id]] = next[id];
+        else G.head = next[id];
+        if (next[id] >= 0) prev[next[id]] = prev[id];
+        of[id] = next[id] = prev[id] = -1;
+        if (--G.size == 1) {
+            const int32_t last = multi.back();
+            multi[G.mpos] = last;
+            g[last].mpos = G.mpos;
+            multi.pop_back();
+            G.mpos = -1;
+        }
+    }
+    void insert_key(uint64_t key, int32_t gi) {
+        if (2 * (used + 1) > hgrp.size()) {
+            std::vector<uint64_t> ok;
+            std::vector<int32_t> og;
+            ok.swap(hkey);
+            og.swap(hgrp);
+            const size_t cap = std::max<size_t>(1024, og.size() * 2);
+            hkey.assign(cap, 0);
+            hgrp.assign(cap, -1);
+            used = 0;
+            for (size_t i = 0; i < og.size(); ++i)
+                if (og[i] >= 0) insert_key(ok[i], og[i]);
+        }
+        const size_t mask = hgrp.size() - 1;
+        size_t i = key & mask;
+        while (hgrp[i] >= 0) i = (i + 1) & mask;
+        hkey[i] = key;
+        hgrp[i] = gi;
+        ++used;
+    }
+    // removal with backward shift: a later slot moves into the hole unless its
+    // home lies cyclically in (hole, slot]
+    void erase_key(uint64_t key, int32_t gi) {
+        const size_t mask = hgrp.size() - 1;
+        size_t i = key & mask;
+        while (hgrp[i] != gi) i = (i + 1) & mask;
+        size_t j = i;
+        for (;;) {
+            j = (j + 1) & mask;
+            if (hgrp[j] < 0) break;
+            const size_t k = hkey[j] & mask;
+            const bool stays = i <= j ? (i < k && k <= j) : (i < k || k <= j);
+            if (stays) continue;
+            hkey[i] = hkey[j];
+            hgrp[i] = hgrp[j];
+            i = j;
+        }
+        hgrp[i] = -1;
+        --used;
+    }
+};
+
 // Device state of ifgp_birch_predict_update: the centroids in slots by entry
 // identity (an entry keeps its slot while splits move it through the leaf
 // order), what is known of every point labelled so far, and work lists.
 struct LabelState {
     Buf f32, f64;          // slot fragments: block cb (identities 16 cb ... 16 cb + 15),
                            // coordinate step s: 64 values in lane order
-    Buf cn32, cn64;        // |c|^2 per slot, +inf in unused slots
+    Buf cn32, cn64;        // |c|^2 per slot, +inf in unused slots (and, in FP32, for the
+                           // members of a twin group other than its representative)
     int64_t cap_blk = 0;   // blocks the slot arrays hold
-    Buf idx;               // int32 per identity: the entry's index in leaf order
-    Buf chg;               // uint8 per identity: centroid new or changed since the last update
-    Buf cmp;               // the changed entries, packed: FP32 fragments (blocks of 16), FP32
-                           // norms, identities
+    Buf gidx;              // int32 per identity: leaf-order index of its twin group's first entry
+    Buf chg;               // uint8 per identity: 0 unchanged since the last update; 1 new or
+                           // changed; 2 changed while its old centroid stays in unchanged twins
+    Buf cmp;               // the entries new in this update, packed: FP32 fragments (blocks
+                           // of 16), FP32 norms, identities
     int64_t cmp_blk = 0;   // blocks cmp holds
-    Buf raw;               // the changed entries as uploaded: FP64 centroids, norms, identities
+    Buf raw;               // the entries as uploaded: FP64 centroids, norms, identities, flags
     Buf best_id;           // int32 per point: its entry, by identity
     Buf best32;            // float per point: FP32 distance to that entry, NaN if not known
-    Buf lists;             // int32 [2][cap_pts]: points to redo in FP32, then in FP64
+    Buf second32;          // float per point: a lower bound on its FP32 distance to every
+                           // other twin group (valid where best32 is known)
+    Buf lists;             // [3][cap_pts]: points to redo in FP32 (int32; later the points
+                           // left to the full FP64 pass), points for the FP64 rule (int32),
+                           // their candidate thresholds (float)
+    Buf ncand, cand;       // per point for the FP64 rule: candidates found, the first ones
     Buf counters;          // int32 [2]: the two lists' lengths
+    Buf part;              // per (point, chunk of entries): a pass's partial result
     int64_t cap_pts = 0, n_prev = 0;
     bool slots_valid = false;
     void *stage = nullptr;  // pinned host staging of an upload
     size_t stage_bytes = 0;
+    int32_t *hcount = nullptr;  // pinned: the lists' lengths, read back between passes
+    int64_t last_counts[4] = {0, 0, 0, 0};  // the last update: points sent to the FP32 pass
+                                            // and to the FP64 rule, twin groups new in it,
+                                            // points left to the full FP64 pass
+    TwinGroups twins;
+    // host work arrays of an upload, kept between updates
+    std::vector<const double *> h_c, h_cn;  // per identity: its centroid and norm in the tree
+    std::vector<int32_t> h_changed, h_touched, h_orphan, h_order, h_kept;
     LabelState() = default;
     LabelState(const LabelState &) = delete;
     LabelState &operator=(const LabelState &) = delete;
     ~LabelState() {
         if (stage) (void)hipHostFree(stage);
+        if (hcount) (void)hipHostFree(hcount);
     }
     void reset() {
-        f32.reset(); f64.reset(); cn32.reset(); cn64.reset(); idx.reset(); chg.reset();
-        cmp.reset(); raw.reset(); best_id.reset(); best32.reset(); lists.reset();
-        counters.reset();
+        f32.reset(); f64.reset(); cn32.reset(); cn64.reset(); gidx.reset(); chg.reset();
+        cmp.reset(); raw.reset(); best_id.reset(); best32.reset(); second32.reset(); lists.reset();
+        counters.reset(); part.reset(); ncand.reset(); cand.reset();
         cap_blk = cmp_blk = cap_pts = n_prev = 0;
         slots_valid = false;
+        twins.clear();
     }
 };
 }  // namespace ifgp
@@ -541,11 +684,22 @@ ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
 // then the FP64 order is the same.  Otherwise (ties, near ties) the point is
 // labelled by the FP64 kernel's rule, first index in leaf order on ties.
 //
+// Twin entries (centroid and norm equal bit for bit) tie exactly for every
+// point; the FP32 passes see one of each twin group, and a point that ends
+// nearest to a group gets the group's first leaf-order index, which is what
+// the FP64 rule picks among them.  Exact ties of that kind, frequent on
+// embeddings with repeated rows, therefore need no FP64 pass.
+//
 // A point labelled before whose nearest entry did not change keeps it against
-// every unchanged entry (they and the point are as they were), so it is
-// compared only with the entries created or changed since, under the same
-// rule; a point whose nearest entry changed, or that was decided in FP64, is
-// labelled again from scratch.
+// every centroid that was there before (they and the point are as they were),
+// so it is compared only with the twin groups new since the last update,
+// under the same rule; a point whose nearest entry changed, or that was
+// decided in FP64, is labelled again from scratch.
+//
+// Each pass gives a wave 64 points (four row tiles sharing every centroid
+// block it loads) and one chunk of the entry blocks, sized so that a pass
+// runs about four waves per SIMD; a second kernel merges the chunks' best and
+// second distances per point and decides.
 //
 // Entries sit in slots by identity, so the device copy of the tree changes
 // only where entries changed; labels map identities to leaf-order indices at
@@ -599,173 +753,377 @@ __device__ __forceinline__ float label_beta(float xn, float cmax, int d) {
 }
 
 template <int S>
-__device__ __forceinline__ void load_points(const float *__restrict__ Z, int d, int64_t p,
-                                            int grp, float *a, float &sq) {
-    sq = 0.f;
+__device__ __forceinline__ void load_row(const float *__restrict__ Z, int d, int64_t p, int grp,
+                                         float *a) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int k = 4 * s + grp;
         a[s] = (p >= 0 && k < d) ? Z[p * d + k] : 0.f;
-        sq += a[s] * a[s];
     }
-    sq += __shfl_xor(sq, 16, 64);
-    sq += __shfl_xor(sq, 32, 64);
 }
 
-// FP32 pass over nblk blocks of 16 entries (fragments F, norms cn, the
-// entries' identities ids, or identity = slot if ids is null): per lane and
-// result slot the best and second distance and the best identity.
-template <int S>
-__device__ __forceinline__ void pass32(const float *a, const float *__restrict__ F,
+// |x| of point p in FP32 (rounding well inside the 1e-4 margin label_beta's
+// callers add)
+__device__ __forceinline__ float row_norm(const float *__restrict__ Z, int d, int64_t p) {
+    float sq = 0.f;
+    for (int k = 0; k < d; ++k) sq += Z[p * d + k] * Z[p * d + k];
+    return sqrtf(sq);
+}
+
+// One pass's result for a point over one chunk of entries.
+struct Part32 {
+    float b, sc;  // best and second FP32 distance (equal on a tie)
+    int32_t id;   // the best entry's identity
+};
+struct Part64 {
+    double dist;  // best FP64 distance
+    int32_t gx;   // leaf-order index of the best entry's twin group
+    int32_t id;   // the best entry's identity
+};
+
+__device__ __forceinline__ void merge32(Part32 &acc, const Part32 &o) {
+    if (o.b < acc.b) {
+        acc.sc = fminf(acc.b, o.sc);
+        acc.b = o.b;
+        acc.id = o.id;
+    } else {
+        acc.sc = fminf(acc.sc, o.b);
+    }
+}
+
+// Appends v to list (length *count) for the lanes where take is set, with one
+// atomic per wave; returns the position written (-1 where take is not set).
+__device__ __forceinline__ int32_t wave_append(bool take, int32_t v, int32_t *__restrict__ list,
+                                               int32_t *__restrict__ count) {
+    const uint64_t mask = __ballot(take);
+    if (mask == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (int32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (!take) return -1;
+    const int32_t at = base + (int32_t)__popcll(mask & ((1ull << lane) - 1));
+    list[at] = v;
+    return at;
+}
+
+// FP32 pass of RT row tiles (16 points each, coordinates in registers) over
+// the entry blocks [cb0, cb1) (fragments F, norms cn, identities ids, or
+// identity = slot if ids is null): per lane, tile and result slot the best
+// and second distance and the best identity.  Blocks are taken two at a time
+// (the next pair loading while one multiplies): cb1 - cb0 is even, or cb1 is
+// the last block and the one after it a spare block of +inf norms; every
+// block that is loaded lies below cb1 + 2.
+template <int S, int RT>
+__device__ __forceinline__ void pass32(const float (&a)[RT][S], const float *__restrict__ F,
                                        const float *__restrict__ cn,
-                                       const int32_t *__restrict__ ids, int64_t nblk, int lane,
-                                       float *b, float *sc, int32_t *bi) {
+                                       const int32_t *__restrict__ ids, int64_t cb0, int64_t cb1,
+                                       int lane, float (&b)[RT][4], float (&sc)[RT][4],
+                                       int32_t (&bi)[RT][4]) {
     const int col = lane & 15;
     float bA[S], bB[S], nA, nB;
-    auto load = [&](float *bf, float &nr, int64_t cb) {
+    int32_t iA, iB;
+    auto load = [&](float *bf, float &nr, int32_t &id, int64_t cb) {
 #pragma unroll
         for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
         nr = cn[cb * 16 + col];
+        id = ids ? ids[cb * 16 + col] : (int32_t)(cb * 16 + col);
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto step = [&](const float *bf, float nrm, int64_t cb) {
-        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+    auto step = [&](const float *bf, float nrm, int32_t id) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bf[s], acc, 0, 0, 0);
-        const int32_t id = ids ? ids[cb * 16 + col] : (int32_t)(cb * 16 + col);
+        for (int t = 0; t < RT; ++t) {
+            f4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) best2_insert(nrm - 2.f * acc[r], id, b[r], sc[r], bi[r]);
+            for (int s = 0; s < S; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s], bf[s], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) best2_insert(nrm - 2.f * acc[r], id, b[t][r], sc[t][r], bi[t][r]);
+        }
     };
-    load(bA, nA, 0);
-    for (int64_t cb = 0; cb < nblk; cb += 2) {
-        load(bB, nB, cb + 1);
-        step(bA, nA, cb);
-        load(bA, nA, cb + 2);
-        step(bB, nB, cb + 1);
+    load(bA, nA, iA, cb0);
+    for (int64_t cb = cb0; cb < cb1; cb += 2) {
+        load(bB, nB, iB, cb + 1);
+        step(bA, nA, iA);
+        load(bA, nA, iA, cb + 2);
+        step(bB, nB, iB);
     }
 }
 
-// Old points [0, n_old), 16 per wave, against the packed changed entries.
-template <int Dp>
-__global__ __launch_bounds__(64 * LW) void label_changed_kernel(
-    const float *__restrict__ Z, int64_t n_old, int d, const float *__restrict__ F,
-    const float *__restrict__ cn, const int32_t *__restrict__ ids, int64_t nblk,
-    const uint8_t *__restrict__ chg, float cmax, int32_t *__restrict__ best_id,
-    float *__restrict__ best32, int32_t *__restrict__ redo, int32_t *__restrict__ nredo) {
+// Points rows[q] (q if rows is null), q < count, 16 RT per wave, against one
+// chunk of cpc entry blocks each (cpc even): wave w takes row group
+// w / chunks and blocks [cpc (w % chunks), ...) below nblk, and writes each
+// point's Part32 of that chunk to part[q * chunks + w % chunks].
+template <int Dp, int RT>
+__global__ __launch_bounds__(64 * LW) void label_part32_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
+    const float *__restrict__ F, const float *__restrict__ cn, const int32_t *__restrict__ ids,
+    int64_t nblk, int64_t chunks, int64_t cpc, Part32 *__restrict__ part) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
-    const int64_t p0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
-    if (p0 >= n_old) return;
-    float a[S], sq;
-    load_points<S>(Z, d, p0 + col < n_old ? p0 + col : -1, grp, a, sq);
-    float b[4], sc[4];
-    int32_t bi[4];
+    const int64_t w = block_index() * LW + (threadIdx.x >> 6);
+    const int64_t ch = w % chunks, q0 = (w / chunks) * 16 * RT;
+    if (q0 >= count) return;
+    float a[RT][S];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        b[r] = sc[r] = __builtin_inff();
-        bi[r] = -1;
+    for (int t = 0; t < RT; ++t) {
+        const int64_t q = q0 + 16 * t + col;
+        load_row<S>(Z, d, q < count ? (rows ? rows[q] : q) : -1, grp, a[t]);
     }
-    pass32<S>(a, F, cn, ids, nblk, lane, b, sc, bi);
+    float b[RT][4], sc[RT][4];
+    int32_t bi[RT][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) best2_reduce(b[r], sc[r], bi[r]);
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = 4 * grp + r;
-        const float sqi = __shfl(sq, i, 64);
-        const int64_t p = p0 + i;
-        if (col == 0 && p < n_old) {
-            const int32_t bo = best_id[p];
-            const float dold = best32[p];
-            const float tol = 2.f * label_beta(sqrtf(sqi) * 1.0001f, cmax, d);
-            bool decided = false;
-            if (!__builtin_isnan(dold) && bo >= 0 && !chg[bo]) {
-                if (dold <= b[r]) {
-                    decided = b[r] - dold > tol;                       // the old entry stays
-                } else if (fminf(sc[r], dold) - b[r] > tol) {          // a changed entry wins
-                    best_id[p] = bi[r];
-                    best32[p] = b[r];
-                    decided = true;
-                }
+        for (int r = 0; r < 4; ++r) {
+            b[t][r] = sc[t][r] = __builtin_inff();
+            bi[t][r] = -1;
+        }
+    const int64_t cb0 = ch * cpc, cb1 = cb0 + cpc < nblk ? cb0 + cpc : nblk;
+    pass32<S, RT>(a, F, cn, ids, cb0, cb1, lane, b, sc, bi);
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            best2_reduce(b[t][r], sc[t][r], bi[t][r]);
+            const int64_t q = q0 + 16 * t + 4 * grp + r;
+            if (col == 0 && q < count) part[q * chunks + ch] = Part32{b[t][r], sc[t][r], bi[t][r]};
+        }
+}
+
+// Old points [0, n_old) after their pass against the twin groups new in this
+// update (chunks partial results each; none if there were none).  Every
+// other group is as it was when the point was last decided in FP32, so it
+// lies at least second32 away (the point's old entry, if unchanged, at
+// best32).  Such a point keeps its entry, or moves to a new group, when the
+// choice has a margin above 2 beta; so does a point whose entry changed
+// (chg 1), over the new groups and second32.  Every other point (FP32
+// distances unknown, or its old centroid still present in unchanged twins:
+// chg 2) goes to the FP32 list.
+__global__ void label_pick_changed_kernel(const float *__restrict__ Z, int d, int64_t n_old,
+                                          int64_t chunks, const Part32 *__restrict__ part,
+                                          const uint8_t *__restrict__ chg, float cmax,
+                                          int32_t *__restrict__ best_id,
+                                          float *__restrict__ best32,
+                                          float *__restrict__ second32,
+                                          int32_t *__restrict__ redo,
+                                          int32_t *__restrict__ nredo) {
+    const int64_t p = block_index() * blockDim.x + threadIdx.x;
+    if (p >= n_old) return;
+    Part32 r{__builtin_inff(), __builtin_inff(), -1};
+    for (int64_t ch = 0; ch < chunks; ++ch) merge32(r, part[p * chunks + ch]);
+    const int32_t bo = best_id[p];
+    const float dold = best32[p], sold = second32[p];
+    const float tol = 2.f * label_beta(row_norm(Z, d, p) * 1.0001f, cmax, d);
+    bool decided = false;
+    if (!__builtin_isnan(dold) && bo >= 0) {
+        const uint8_t cg = chg[bo];
+        if (cg == 0 && dold <= r.b) {
+            if (r.b - dold > tol) {                            // the old entry stays
+                second32[p] = fminf(sold, r.b);
+                decided = true;
             }
-            if (!decided) redo[atomicAdd(nredo, 1)] = (int32_t)p;
+        } else if (cg == 0) {
+            // a new group wins (second32 is below dold where the old entry won
+            // over a closer FP32 runner-up in FP64)
+            const float rest = fminf(r.sc, fminf(dold, sold));
+            if (rest - r.b > tol) {
+                best_id[p] = r.id;
+                best32[p] = r.b;
+                second32[p] = rest;
+                decided = true;
+            }
+        } else if (cg == 1 && fminf(r.sc, sold) - r.b > tol) { // the entry moved: a new group wins
+            best_id[p] = r.id;
+            best32[p] = r.b;
+            second32[p] = fminf(r.sc, sold);
+            decided = true;
         }
     }
+    wave_append(!decided, (int32_t)p, redo, nredo);
 }
 
 // Appends the new points [n_old, n) to the FP32 list.
 __global__ void label_push_kernel(int64_t n_old, int64_t n, int32_t *__restrict__ list,
                                   int32_t *__restrict__ count) {
     const int64_t p = n_old + block_index() * blockDim.x + threadIdx.x;
-    if (p < n) list[atomicAdd(count, 1)] = (int32_t)p;
+    if (p < n) wave_append(true, (int32_t)p, list, count);
 }
 
-// Points listed in list32[0, *n32), 16 per wave, against every slot in FP32;
-// undecided ones go to list64.
+// Points list[q], q < count, after their FP32 pass against every slot:
+// decided when the runner-up is more than 2 beta further away, else sent to
+// the FP64 list with the FP32 distance below which its candidates for the
+// FP64 rule lie (thr64: best + 3 beta, so that the sum's rounding still
+// leaves it above best + 2 beta).
+__global__ void label_pick32_kernel(const float *__restrict__ Z, int d,
+                                    const int32_t *__restrict__ list, int64_t count,
+                                    int64_t chunks, const Part32 *__restrict__ part, float cmax,
+                                    int32_t *__restrict__ best_id, float *__restrict__ best32,
+                                    float *__restrict__ second32, int32_t *__restrict__ list64,
+                                    float *__restrict__ thr64, int32_t *__restrict__ n64) {
+    const int64_t q = block_index() * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    Part32 r{__builtin_inff(), __builtin_inff(), -1};
+    for (int64_t ch = 0; ch < chunks; ++ch) merge32(r, part[q * chunks + ch]);
+    const int32_t p = list[q];
+    const float tol = 2.f * label_beta(row_norm(Z, d, p) * 1.0001f, cmax, d);
+    const bool decided = r.sc - r.b > tol;
+    if (decided) {
+        best_id[p] = r.id;
+        best32[p] = r.b;
+        second32[p] = r.sc;
+    }
+    const int32_t at = wave_append(!decided, p, list64, n64);
+    if (at >= 0) thr64[at] = r.b + 1.5f * tol;
+}
+
+// The FP64 rule over candidates.  An entry can be a point's nearest in FP64
+// only if its FP32 distance is within 2 beta of the FP32 nearest (each FP32
+// distance lies within beta of the FP64 one), so those entries are the
+// point's candidates; the others are further in FP64 than the FP32 nearest.
+constexpr int LABEL_CAND = 8;  // candidates kept per point; more send it to the full FP64 pass
+struct Cand {
+    int32_t id;   // slot (identity) of a twin group's representative
+    float d32;    // its FP32 distance
+};
+
+// Points rows[q], q < count, 16 per wave, against one chunk of cpc slot
+// blocks each in FP32 (representatives only; wave w takes row group
+// w / chunks, chunk w % chunks): every entry (slot below nid) at most thr[q]
+// away is counted in ncand[q], and the first LABEL_CAND are kept in cand[q].
 template <int Dp>
-__global__ __launch_bounds__(64 * LW) void label_full32_kernel(
-    const float *__restrict__ Z, int d, const int32_t *__restrict__ list32,
-    const int32_t *__restrict__ n32, const float *__restrict__ F, const float *__restrict__ cn,
-    int64_t nblk, float cmax, int32_t *__restrict__ best_id, float *__restrict__ best32,
-    int32_t *__restrict__ list64, int32_t *__restrict__ n64) {
+__global__ __launch_bounds__(64 * LW) void label_cand_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
+    const float *__restrict__ thr, const float *__restrict__ F, const float *__restrict__ cn,
+    int64_t nid, int64_t nblk, int64_t chunks, int64_t cpc, int32_t *__restrict__ ncand,
+    Cand *__restrict__ cand) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
-    const int64_t q0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
-    const int64_t count = *n32;
+    const int64_t w = block_index() * LW + (threadIdx.x >> 6);
+    const int64_t ch = w % chunks, q0 = (w / chunks) * 16;
     if (q0 >= count) return;
-    const int64_t mine = q0 + col < count ? list32[q0 + col] : -1;
-    float a[S], sq;
-    load_points<S>(Z, d, mine, grp, a, sq);
-    float b[4], sc[4];
-    int32_t bi[4];
+    float a[S];
+    load_row<S>(Z, d, q0 + col < count ? rows[q0 + col] : -1, grp, a);
+    float t[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        b[r] = sc[r] = __builtin_inff();
-        bi[r] = -1;
+        const int64_t q = q0 + 4 * grp + r;
+        t[r] = q < count ? thr[q] : -__builtin_inff();
     }
-    pass32<S>(a, F, cn, nullptr, nblk, lane, b, sc, bi);
+    const int64_t cb0 = ch * cpc, cb1 = cb0 + cpc < nblk ? cb0 + cpc : nblk;
+    for (int64_t cb = cb0; cb < cb1; ++cb) {
+        float bf[S];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) best2_reduce(b[r], sc[r], bi[r]);
+        for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
+        const float nrm = cn[cb * 16 + col];
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = 4 * grp + r;
-        const float sqi = __shfl(sq, i, 64);
-        const int64_t q = q0 + i;
-        if (col == 0 && q < count) {
-            const int32_t p = list32[q];
-            const float tol = 2.f * label_beta(sqrtf(sqi) * 1.0001f, cmax, d);
-            if (sc[r] - b[r] > tol) {
-                best_id[p] = bi[r];
-                best32[p] = b[r];
-            } else {
-                list64[atomicAdd(n64, 1)] = p;
+        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bf[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float dist = nrm - 2.f * acc[r];
+            if (dist <= t[r] && cb * 16 + col < nid) {
+                const int64_t q = q0 + 4 * grp + r;
+                const int32_t k = atomicAdd(&ncand[q], 1);
+                if (k < LABEL_CAND) cand[q * LABEL_CAND + k] = Cand{(int32_t)(cb * 16 + col), dist};
             }
         }
     }
 }
 
-// Points listed in list64[0, *n64) against every slot in FP64, as the FP64
-// kernel compares them (nearest, first index in leaf order on ties); their
-// FP32 distance is left unknown, so a later update labels them afresh.
+// Points rows[q], q < count, 16 per wave, labelled by the FP64 rule over
+// their candidates (at most LABEL_CAND; points with more go to the list
+// full).  The FP64 distance of point j to its candidate is the diagonal
+// element D[j][j] of a product whose column j holds point j's candidate:
+// the same sum, in the same order, as in the FP64 kernel.  The FP32
+// distances stay known: the winner's, and below every other group the least
+// of the other candidates' and thr[q].
 template <int Dp>
-__global__ __launch_bounds__(64 * LW) void label_full64_kernel(
-    const float *__restrict__ Z, int d, const int32_t *__restrict__ list64,
-    const int32_t *__restrict__ n64, const double *__restrict__ F,
-    const double *__restrict__ cn, const int32_t *__restrict__ idx, int64_t nblk, int64_t nid,
-    int32_t *__restrict__ best_id, float *__restrict__ best32) {
+__global__ __launch_bounds__(64 * LW) void label_cand64_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
+    const float *__restrict__ thr, const int32_t *__restrict__ ncand,
+    const Cand *__restrict__ cand, const double *__restrict__ F, const double *__restrict__ cn,
+    const int32_t *__restrict__ gidx, int32_t *__restrict__ best_id, float *__restrict__ best32,
+    float *__restrict__ second32, int32_t *__restrict__ full, int32_t *__restrict__ nfull) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int64_t q0 = (block_index() * LW + (threadIdx.x >> 6)) * 16;
-    const int64_t count = *n64;
     if (q0 >= count) return;
-    const int64_t p = q0 + col < count ? list64[q0 + col] : -1;
+    const int64_t q = q0 + col;  // the point of this lane's row and column
+    const bool live = q < count;
+    const int64_t p = live ? rows[q] : -1;
     double a[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int k = 4 * s + grp;
         a[s] = (p >= 0 && k < d) ? (double)Z[p * d + k] : 0.0;
     }
-    // per result slot: best distance, its entry (identity) and that entry's
-    // leaf-order index, so that (distance, index) is compared in one step
+    const int nc = live ? ncand[q] : 0;
+    const int use = nc > LABEL_CAND ? 0 : nc;
+    // D[j][j] is in lane j + 16 (j % 4), slot j / 4
+    const bool diag = (col & 3) == grp;
+    double bd = __builtin_inf();
+    int32_t bx = INT32_MAX, bc = -1;
+    for (int c = 0; c < LABEL_CAND; ++c) {
+        const int32_t id = c < use ? cand[q * LABEL_CAND + c].id : -1;
+        double bf[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            bf[s] = id >= 0 ? F[((int64_t)(id / 16) * S + s) * 64 + id % 16 + 16 * grp] : 0.0;
+        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bf[s], acc, 0, 0, 0);
+        const int slot = col >> 2;
+        const double v = slot == 0 ? acc[0] : slot == 1 ? acc[1] : slot == 2 ? acc[2] : acc[3];
+        if (diag && id >= 0) {
+            const double dist = cn[id] - 2.0 * v;
+            const int32_t gx = gidx[id];
+            if (dist < bd || (dist == bd && gx < bx)) {
+                bd = dist;
+                bx = gx;
+                bc = c;
+            }
+        }
+    }
+    if (!(diag && live)) return;
+    const bool decided = bc >= 0;
+    if (decided) {
+        float won = 0.f, rest = thr[q];
+        for (int c = 0; c < use; ++c) {
+            const Cand e = cand[q * LABEL_CAND + c];
+            if (c == bc) won = e.d32;
+            else rest = fminf(rest, e.d32);
+        }
+        best_id[p] = cand[q * LABEL_CAND + bc].id;
+        best32[p] = won;
+        second32[p] = rest;
+    }
+    wave_append(!decided, (int32_t)p, full, nfull);
+}
+
+// Points rows[q], q < count, 16 per wave, against one chunk of cpc slot
+// blocks each in FP64, as the FP64 kernel compares them (nearest, then first
+// in leaf order; a twin group's members share its first entry's index gx):
+// wave w takes row group w / chunks and blocks [cpc (w % chunks), ...) below
+// nblk.
+template <int Dp>
+__global__ __launch_bounds__(64 * LW) void label_part64_kernel(
+    const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
+    const double *__restrict__ F, const double *__restrict__ cn, const int32_t *__restrict__ gidx,
+    int64_t nid, int64_t nblk, int64_t chunks, int64_t cpc, Part64 *__restrict__ part) {
+    constexpr int S = Dp / 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int64_t w = block_index() * LW + (threadIdx.x >> 6);
+    const int64_t ch = w % chunks, q0 = (w / chunks) * 16;
+    if (q0 >= count) return;
+    const int64_t p = q0 + col < count ? rows[q0 + col] : -1;
+    double a[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = 4 * s + grp;
+        a[s] = (p >= 0 && k < d) ? (double)Z[p * d + k] : 0.0;
+    }
     double best[4];
     int32_t bi[4], bx[4];
 #pragma unroll
@@ -774,13 +1132,14 @@ __global__ __launch_bounds__(64 * LW) void label_full64_kernel(
         bi[r] = -1;
         bx[r] = INT32_MAX;
     }
-    for (int64_t cb = 0; cb < nblk; ++cb) {
+    const int64_t cb0 = ch * cpc, cb1 = cb0 + cpc < nblk ? cb0 + cpc : nblk;
+    for (int64_t cb = cb0; cb < cb1; ++cb) {
         double bf[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) bf[s] = F[(cb * S + s) * 64 + lane];
         const double nrm = cn[cb * 16 + col];
         const int64_t c64 = cb * 16 + col;
-        const int32_t cx = c64 < nid ? idx[c64] : INT32_MAX;  // unused slots sort last
+        const int32_t cx = c64 < nid ? gidx[c64] : INT32_MAX;  // unused slots sort last
         d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bf[s], acc, 0, 0, 0);
@@ -808,59 +1167,78 @@ __global__ __launch_bounds__(64 * LW) void label_full64_kernel(
         }
         // FP64 result layout: D[i][j] in lane j + 16 (i % 4), slot i / 4
         const int64_t q = q0 + 4 * r + grp;
-        if (col == 0 && q < count) {
-            const int32_t pt = list64[q];
-            best_id[pt] = i;
-            best32[pt] = __builtin_nanf("");
-        }
+        if (col == 0 && q < count) part[q * chunks + ch] = Part64{v, x, i};
     }
+}
+
+// Points list[q], q < count, labelled from their FP64 partial results; their
+// FP32 distance is left unknown, so a later update labels them afresh.
+__global__ void label_pick64_kernel(const int32_t *__restrict__ list, int64_t count,
+                                    int64_t chunks, const Part64 *__restrict__ part,
+                                    int32_t *__restrict__ best_id, float *__restrict__ best32) {
+    const int64_t q = block_index() * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    Part64 r{__builtin_inf(), INT32_MAX, -1};
+    for (int64_t ch = 0; ch < chunks; ++ch) {
+        const Part64 o = part[q * chunks + ch];
+        if (o.dist < r.dist || (o.dist == r.dist && o.gx < r.gx)) r = o;
+    }
+    const int32_t p = list[q];
+    best_id[p] = r.id;
+    best32[p] = __builtin_nanf("");
 }
 
 __global__ void label_map_kernel(int64_t n, const int32_t *__restrict__ best_id,
-                                 const int32_t *__restrict__ idx, int32_t *__restrict__ labels) {
+                                 const int32_t *__restrict__ gidx, int32_t *__restrict__ labels) {
     const int64_t p = block_index() * blockDim.x + threadIdx.x;
     if (p < n) {
         const int32_t e = best_id[p];
-        labels[p] = e >= 0 ? idx[e] : -1;   // -1 only for rows with no finite distance
+        labels[p] = e >= 0 ? gidx[e] : -1;   // -1 only for rows with no finite distance
     }
 }
 
-// The uploaded changed entries (centroid FP64 m x d, norms, identities) into
-// their slots (FP64 and FP32 fragments and norms) and into the packed FP32
-// array (padding of the last blocks: zero coordinates, norm +inf).  One
-// thread per (entry, coordinate), entries padded to whole blocks.
-__global__ void label_scatter_kernel(int64_t m, int64_t m_pad, int d, int S,
-                                     const double *__restrict__ c, const double *__restrict__ nrm,
-                                     const int32_t *__restrict__ ids, double *__restrict__ f64,
+// The uploaded entries (centroid FP64 m x d, norms, identities, flags: 1 for
+// a twin group's representative) into their slots (FP64 and FP32 fragments
+// and norms; FP32 norm +inf for the other twins), the first m_pack of them
+// also into the packed FP32 array, whose blocks are padded to m_pack_pad
+// entries with zero coordinates and norm +inf.  One thread per (entry,
+// coordinate) over max(m, m_pack_pad) entries.
+__global__ void label_scatter_kernel(int64_t m, int64_t m_pack, int64_t m_pack_pad, int64_t total,
+                                     int d, int S, const double *__restrict__ c,
+                                     const double *__restrict__ nrm,
+                                     const int32_t *__restrict__ ids,
+                                     const uint8_t *__restrict__ rep, double *__restrict__ f64,
                                      float *__restrict__ f32, double *__restrict__ cn64,
                                      float *__restrict__ cn32, float *__restrict__ pf,
                                      float *__restrict__ pcn, int32_t *__restrict__ pid) {
     const int Dp = 4 * S;
     const int64_t t = block_index() * blockDim.x + threadIdx.x;
-    if (t >= m_pad * Dp) return;
+    if (t >= total * Dp) return;
     const int64_t q = t / Dp;
     const int j = (int)(t % Dp);
-    const int64_t pb = q / 16, pcol = q % 16;
-    const int64_t po = (pb * S + j / 4) * 64 + pcol + 16 * (j % 4);
-    if (q >= m) {
+    const int64_t po = ((q / 16) * S + j / 4) * 64 + q % 16 + 16 * (j % 4);
+    if (q < m) {
+        const int64_t id = ids[q], cb = id / 16, ccol = id % 16;
+        const int64_t so = (cb * S + j / 4) * 64 + ccol + 16 * (j % 4);
+        const double v = j < d ? c[q * d + j] : 0.0;
+        f64[so] = v;
+        f32[so] = (float)v;
+        if (q < m_pack) pf[po] = (float)v;
+        if (j == 0) {
+            cn64[id] = nrm[q];
+            cn32[id] = rep[q] ? (float)nrm[q] : __builtin_inff();
+            if (q < m_pack) {
+                pcn[q] = (float)nrm[q];
+                pid[q] = (int32_t)id;
+            }
+        }
+    }
+    if (q >= m_pack && q < m_pack_pad) {
         pf[po] = 0.f;
         if (j == 0) {
             pcn[q] = __builtin_inff();
             pid[q] = 0;
         }
-        return;
-    }
-    const int64_t id = ids[q], cb = id / 16, ccol = id % 16;
-    const int64_t so = (cb * S + j / 4) * 64 + ccol + 16 * (j % 4);
-    const double v = j < d ? c[q * d + j] : 0.0;
-    f64[so] = v;
-    f32[so] = (float)v;
-    pf[po] = (float)v;
-    if (j == 0) {
-        cn64[id] = nrm[q];
-        cn32[id] = (float)nrm[q];
-        pcn[q] = (float)nrm[q];
-        pid[q] = (int32_t)id;
     }
 }
 
@@ -905,24 +1283,151 @@ ifgp_status ensure_slots(ifgp_birch_s *b, int64_t nblk, hipStream_t s) {
     return IFGP_OK;
 }
 
-// Host walk of the leaves: identities -> leaf-order indices, the largest
-// centroid norm, and the entries to upload (all of them if the slots are not
-// filled yet, else those changed since the last update), staged in pinned
-// memory and copied to the device, then scattered into place.
-ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, int64_t *m_out, double *cmax) {
+uint64_t twin_key(const double *c, int d, double cn) {
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    for (int k = 0; k <= d; ++k) {
+        uint64_t w;
+        std::memcpy(&w, k < d ? &c[k] : &cn, sizeof w);
+        h = (h ^ w) * 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+    }
+    return h;
+}
+
+// What an upload sent: m entries, the first m_pack of them new in this update
+// (twin groups none of whose members was there before) and packed for the
+// pass over old points; the largest centroid norm.
+struct Upload {
+    int64_t m = 0, m_pack = 0;
+    double cmax = 0.0;
+};
+
+// Host walk of the leaves (identities -> leaf-order indices, the largest
+// centroid norm), the twin groups brought up to date with the entries changed
+// since the last update (all of them if the slots are not filled yet), and
+// the upload: per identity its group's first leaf-order index and whether it
+// changed; per uploaded entry its centroid, norm, identity and whether it
+// represents its group.  Staged in pinned memory, copied to the device, then
+// scattered into place.
+ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     LabelState &L = b->ls;
+    TwinGroups &T = L.twins;
     const int d = b->d, Dp = b->Dp, S = Dp / 4;
     const int64_t nid = b->next_id;
     const bool all = !L.slots_valid;
-    const int64_t m = all ? nid : (int64_t)b->chg_list.size();
-    const int64_t m_pad = (ceil_div(m, (int64_t)16) + LABEL_SPARE) * 16;
-    // staging layout: idx (nid int32), chg (nid bytes, padded to 8), centroids
-    // (m x d doubles), norms (m doubles), identities (m int32)
     const size_t o_chg = sizeof(int32_t) * (size_t)nid;
-    const size_t o_c = (o_chg + (size_t)nid + 7) / 8 * 8;
+    const size_t o_c0 = (o_chg + (size_t)nid + 7) / 8 * 8;
+    L.h_c.resize((size_t)nid);
+    L.h_cn.resize((size_t)nid);
+    std::vector<int32_t> idx((size_t)nid);
+    double mx = 0.0;
+    int64_t k = 0;
+    for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
+        for (int e = 0; e < l->size(); ++e, ++k) {
+            const int32_t id = l->id[e];
+            idx[id] = (int32_t)k;
+            L.h_c[id] = &l->c[(size_t)e * d];
+            L.h_cn[id] = &l->cn[e];
+            mx = std::max(mx, l->cn[e]);
+        }
+    std::vector<int32_t> &changed = L.h_changed;
+    if (all) {
+        T.clear();
+        changed.resize((size_t)nid);
+        for (int32_t i = 0; i < (int32_t)nid; ++i) changed[i] = i;
+    } else {
+        changed.assign(b->chg_list.begin(), b->chg_list.end());
+    }
+    auto is_chg = [&](int32_t id) { return all || b->chg[(size_t)id] != 0; };
+    T.resize((size_t)nid);
+    // the changed entries leave their groups
+    std::vector<int32_t> &orphan = L.h_orphan;
+    orphan.clear();
+    L.h_kept.clear();
+    for (int32_t id : changed) {
+        const int32_t gi = T.of[id];
+        if (gi < 0) continue;
+        T.remove(gi, id);
+        TwinGroups::Group &G = T.g[gi];
+        if (G.size == 0) {
+            T.drop(gi);
+            continue;
+        }
+        for (int32_t x = G.head; x >= 0; x = T.next[x])
+            if (!is_chg(x)) {
+                L.h_kept.push_back(id);  // its old centroid stays in unchanged twins
+                break;
+            }
+        if (G.rep == id) {
+            G.rep = -1;
+            orphan.push_back(gi);
+        }
+    }
+    // ... and join the groups of their current centroids
+    std::vector<int32_t> &touched = L.h_touched;
+    touched.clear();
+    for (int32_t id : changed) {
+        const double *c = L.h_c[id];
+        const double cn = *L.h_cn[id];
+        const uint64_t key = twin_key(c, d, cn);
+        int32_t gi = -1;
+        if (!T.hgrp.empty()) {
+            const size_t mask = T.hgrp.size() - 1;
+            for (size_t i = key & mask; T.hgrp[i] >= 0; i = (i + 1) & mask) {
+                if (T.hkey[i] != key) continue;
+                const int32_t o = T.g[T.hgrp[i]].head;
+                if (std::memcmp(L.h_cn[o], &cn, sizeof cn) == 0 &&
+                    std::memcmp(L.h_c[o], c, sizeof(double) * d) == 0) {
+                    gi = T.hgrp[i];
+                    break;
+                }
+            }
+        }
+        if (gi < 0) gi = T.make(key);
+        T.add(gi, id);
+        if (T.g[gi].fresh++ == 0) touched.push_back(gi);
+    }
+    // representatives (an unchanged member where there is one: then only its
+    // FP32 norm changes on the device), and the upload order: representatives
+    // of the groups new in this update, the other changed entries, then the
+    // unchanged members that became representatives
+    std::vector<int32_t> &order = L.h_order;
+    order.clear();
+    std::vector<int32_t> promoted;
+    auto choose = [&](TwinGroups::Group &G) {
+        for (int32_t x = G.head; x >= 0; x = T.next[x])
+            if (!is_chg(x)) {
+                G.rep = x;
+                promoted.push_back(x);
+                return;
+            }
+        G.rep = G.head;
+    };
+    for (int32_t gi : touched) {
+        TwinGroups::Group &G = T.g[gi];
+        if (G.rep < 0) choose(G);
+        if (G.fresh == G.size) order.push_back(G.rep);
+    }
+    for (int32_t gi : orphan) {
+        TwinGroups::Group &G = T.g[gi];
+        if (G.rep < 0 && G.size > 0) choose(G);
+    }
+    const int64_t m_pack = (int64_t)order.size();
+    for (int32_t id : changed) {
+        const TwinGroups::Group &G = T.g[T.of[id]];
+        if (!(G.rep == id && G.fresh == G.size)) order.push_back(id);
+    }
+    for (int32_t gi : touched) T.g[gi].fresh = 0;
+    order.insert(order.end(), promoted.begin(), promoted.end());
+    const int64_t m = (int64_t)order.size();
+    const int64_t m_pack_pad = (ceil_div(m_pack, (int64_t)16) + LABEL_SPARE) * 16;
+    // staging layout: gidx (nid int32), chg (nid bytes, padded to 8), centroids
+    // (m x d doubles), norms (m doubles), identities (m int32), flags (m bytes)
+    const size_t o_c = o_c0;
     const size_t o_n = o_c + sizeof(double) * (size_t)m * d;
     const size_t o_id = o_n + sizeof(double) * (size_t)m;
-    const size_t bytes = o_id + sizeof(int32_t) * (size_t)m + 8;
+    const size_t o_rep = o_id + sizeof(int32_t) * (size_t)m;
+    const size_t bytes = o_rep + (size_t)m + 8;
     if (L.stage_bytes < bytes) {
         if (L.stage) IFGP_HIP(hipHostFree(L.stage));
         L.stage = nullptr;
@@ -932,66 +1437,185 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, int64_t *m_out, doubl
         L.stage_bytes = cap;
     }
     char *h = static_cast<char *>(L.stage);
-    int32_t *idx = reinterpret_cast<int32_t *>(h);
+    int32_t *gx = reinterpret_cast<int32_t *>(h);
     uint8_t *chg = reinterpret_cast<uint8_t *>(h + o_chg);
     double *c = reinterpret_cast<double *>(h + o_c), *nrm = reinterpret_cast<double *>(h + o_n);
     int32_t *ids = reinterpret_cast<int32_t *>(h + o_id);
-    double mx = 0.0;
-    int64_t k = 0, q = 0;
-    for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
-        for (int e = 0; e < l->size(); ++e, ++k) {
-            const int32_t id = l->id[e];
-            idx[id] = (int32_t)k;
-            mx = std::max(mx, l->cn[e]);
-            if (all) {
-                ids[id] = id;
-                std::memcpy(c + (size_t)id * d, &l->c[(size_t)e * d], sizeof(double) * d);
-                nrm[id] = l->cn[e];
-            }
-        }
-    if (!all)
-        for (int32_t id : b->chg_list) ids[q++] = id;
-    for (int64_t i = 0; i < nid; ++i) chg[i] = all ? 1 : b->chg[(size_t)i];
-    if (!all) {
-        // centroids of the changed entries: find each by a second walk
-        std::vector<int32_t> pos((size_t)nid, -1);
-        for (int64_t i = 0; i < m; ++i) pos[(size_t)ids[i]] = (int32_t)i;
-        for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
-            for (int e = 0; e < l->size(); ++e) {
-                const int32_t at = pos[(size_t)l->id[e]];
-                if (at >= 0) {
-                    std::memcpy(c + (size_t)at * d, &l->c[(size_t)e * d], sizeof(double) * d);
-                    nrm[at] = l->cn[e];
-                }
-            }
+    uint8_t *rep = reinterpret_cast<uint8_t *>(h + o_rep);
+    std::memcpy(gx, idx.data(), sizeof(int32_t) * (size_t)nid);
+    for (int32_t gi : T.multi) {
+        int32_t first = INT32_MAX;
+        for (int32_t x = T.g[gi].head; x >= 0; x = T.next[x]) first = std::min(first, idx[x]);
+        for (int32_t x = T.g[gi].head; x >= 0; x = T.next[x]) gx[x] = first;
+    }
+    for (int64_t i = 0; i < nid; ++i) chg[i] = is_chg((int32_t)i) ? 1 : 0;
+    for (int32_t id : L.h_kept) chg[id] = 2;
+    for (int64_t q = 0; q < m; ++q) {
+        const int32_t id = order[q];
+        std::memcpy(c + (size_t)q * d, L.h_c[id], sizeof(double) * d);
+        nrm[q] = *L.h_cn[id];
+        ids[q] = id;
+        rep[q] = T.g[T.of[id]].rep == id ? 1 : 0;
     }
     for (int32_t id : b->chg_list) b->chg[(size_t)id] = 0;
     b->chg_list.clear();
     IFGP_TRY(ensure_slots(b, ceil_div(nid, (int64_t)16), s));
     IFGP_TRY(ensure(L.raw, bytes, s));
-    IFGP_TRY(ensure(L.idx, sizeof(int32_t) * (size_t)nid, s));
+    IFGP_TRY(ensure(L.gidx, sizeof(int32_t) * (size_t)nid, s));
     IFGP_TRY(ensure(L.chg, (size_t)nid, s));
-    const size_t cmp_bytes = (sizeof(float) * Dp + sizeof(float) + sizeof(int32_t)) * (size_t)m_pad;
+    const size_t cmp_bytes = (sizeof(float) * Dp + sizeof(float) + sizeof(int32_t)) * (size_t)m_pack_pad;
     IFGP_TRY(ensure(L.cmp, cmp_bytes, s));
-    L.cmp_blk = m_pad / 16;
+    L.cmp_blk = m_pack_pad / 16;
     IFGP_HIP(hipMemcpyAsync(L.raw.p, h, bytes, hipMemcpyHostToDevice, s));
     const char *r = static_cast<const char *>(L.raw.p);
-    IFGP_HIP(hipMemcpyAsync(L.idx.p, r, sizeof(int32_t) * (size_t)nid, hipMemcpyDeviceToDevice, s));
+    IFGP_HIP(hipMemcpyAsync(L.gidx.p, r, sizeof(int32_t) * (size_t)nid, hipMemcpyDeviceToDevice, s));
     IFGP_HIP(hipMemcpyAsync(L.chg.p, r + o_chg, (size_t)nid, hipMemcpyDeviceToDevice, s));
     float *pf = L.cmp.as<float>();
-    float *pcn = pf + (size_t)m_pad * Dp;
-    int32_t *pid = reinterpret_cast<int32_t *>(pcn + m_pad);
-    label_scatter_kernel<<<grid_for(ceil_div(m_pad * Dp, 256)), 256, 0, s>>>(
-        m, m_pad, d, S, reinterpret_cast<const double *>(r + o_c),
+    float *pcn = pf + (size_t)m_pack_pad * Dp;
+    int32_t *pid = reinterpret_cast<int32_t *>(pcn + m_pack_pad);
+    const int64_t total = std::max(m, m_pack_pad);
+    label_scatter_kernel<<<grid_for(ceil_div(total * Dp, 256)), 256, 0, s>>>(
+        m, m_pack, m_pack_pad, total, d, S, reinterpret_cast<const double *>(r + o_c),
         reinterpret_cast<const double *>(r + o_n), reinterpret_cast<const int32_t *>(r + o_id),
-        L.f64.as<double>(), L.f32.as<float>(), L.cn64.as<double>(), L.cn32.as<float>(), pf, pcn,
-        pid);
+        reinterpret_cast<const uint8_t *>(r + o_rep), L.f64.as<double>(), L.f32.as<float>(),
+        L.cn64.as<double>(), L.cn32.as<float>(), pf, pcn, pid);
     IFGP_LAUNCHED();
     // the staging memory is reused by the next update: wait for the copy
     IFGP_HIP(hipStreamSynchronize(s));
     L.slots_valid = true;
-    *m_out = m;
-    *cmax = std::sqrt(mx);
+    up->m = m;
+    up->m_pack = m_pack;
+    up->cmax = std::sqrt(mx);
+    return IFGP_OK;
+}
+
+constexpr int64_t LABEL_WAVES = 4096;  // waves a pass aims for: four per SIMD
+constexpr int LABEL_RT = 4;            // row tiles of 16 points per wave in the FP32 passes
+
+// Chunks of an even number of entry blocks (at least 8) for a pass over nblk
+// blocks, so that `groups` row groups times the chunks come to about
+// LABEL_WAVES waves.
+void label_chunks(int64_t groups, int64_t nblk, int64_t *chunks, int64_t *cpc) {
+    const int64_t want = std::max<int64_t>(1, ceil_div(LABEL_WAVES, std::max<int64_t>(groups, 1)));
+    int64_t c = std::max<int64_t>(8, ceil_div(std::max<int64_t>(nblk, 1), want));
+    c += c & 1;
+    *cpc = c;
+    *chunks = std::max<int64_t>(1, ceil_div(nblk, c));
+}
+
+// The list lengths, read back between passes (the next pass is sized by them).
+ifgp_status read_counts(LabelState &L, hipStream_t s) {
+    IFGP_HIP(hipMemcpyAsync(L.hcount, L.counters.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    IFGP_HIP(hipStreamSynchronize(s));
+    return IFGP_OK;
+}
+
+// The passes of an update: old points against the new entries, the FP32
+// list against every slot, the FP64 list against every slot; then labels.
+template <int Dp>
+ifgp_status label_passes(ifgp_birch_s *b, const float *Z, int64_t n, int64_t n_old,
+                         const Upload &up, int32_t *labels, hipStream_t s) {
+    LabelState &L = b->ls;
+    const int d = b->d;
+    const int64_t nid = b->next_id, nblk = ceil_div(nid, (int64_t)16);
+    int32_t *cnt = L.counters.as<int32_t>();
+    int32_t *list32 = L.lists.as<int32_t>(), *list64 = list32 + L.cap_pts;
+    float *thr64 = reinterpret_cast<float *>(list32 + 2 * L.cap_pts);
+    int32_t *best_id = L.best_id.as<int32_t>();
+    float *best32 = L.best32.as<float>();
+    // nearest entry in FP32 within 2 beta of the FP64 one: cmax bounds every |c|
+    const float cm = (float)(up.cmax * (1.0 + 1e-6)) + 1e-30f;
+    label_fill_kernel<int32_t><<<1, 64, 0, s>>>(cnt, 2, 0);
+    IFGP_LAUNCHED();
+    if (n_old > 0) {
+        int64_t chunks = 0, cpc = 0;
+        const int64_t pblk = ceil_div(up.m_pack, (int64_t)16);
+        if (pblk > 0) {
+            const int64_t groups = ceil_div(n_old, (int64_t)16 * LABEL_RT);
+            label_chunks(groups, pblk, &chunks, &cpc);
+            IFGP_TRY(ensure(L.part, sizeof(Part32) * (size_t)(n_old * chunks), s));
+            const float *pf = L.cmp.as<float>();
+            const float *pcn = pf + (size_t)L.cmp_blk * 16 * Dp;
+            const int32_t *pid = reinterpret_cast<const int32_t *>(pcn + L.cmp_blk * 16);
+            label_part32_kernel<Dp, LABEL_RT>
+                <<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
+                    Z, d, nullptr, n_old, pf, pcn, pid, pblk, chunks, cpc, L.part.as<Part32>());
+            IFGP_LAUNCHED();
+        }
+        label_pick_changed_kernel<<<grid_for(ceil_div(n_old, (int64_t)256)), 256, 0, s>>>(
+            Z, d, n_old, chunks, L.part.as<Part32>(), L.chg.as<uint8_t>(), cm, best_id, best32,
+            L.second32.as<float>(), list32, cnt);
+        IFGP_LAUNCHED();
+    }
+    if (n > n_old) {
+        label_push_kernel<<<grid_for(ceil_div(n - n_old, (int64_t)256)), 256, 0, s>>>(n_old, n,
+                                                                                      list32, cnt);
+        IFGP_LAUNCHED();
+    }
+    IFGP_TRY(read_counts(L, s));
+    const int64_t n32 = L.hcount[0];
+    if (n32 > 0) {
+        int64_t chunks = 0, cpc = 0;
+        const int64_t groups = ceil_div(n32, (int64_t)16 * LABEL_RT);
+        label_chunks(groups, nblk, &chunks, &cpc);
+        IFGP_TRY(ensure(L.part, sizeof(Part32) * (size_t)(n32 * chunks), s));
+        label_part32_kernel<Dp, LABEL_RT>
+            <<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
+                Z, d, list32, n32, L.f32.as<float>(), L.cn32.as<float>(), nullptr, nblk, chunks,
+                cpc, L.part.as<Part32>());
+        IFGP_LAUNCHED();
+        label_pick32_kernel<<<grid_for(ceil_div(n32, (int64_t)256)), 256, 0, s>>>(
+            Z, d, list32, n32, chunks, L.part.as<Part32>(), cm, best_id, best32,
+            L.second32.as<float>(), list64, thr64, cnt + 1);
+        IFGP_LAUNCHED();
+        IFGP_TRY(read_counts(L, s));
+    }
+    const int64_t n64 = n32 > 0 ? L.hcount[1] : 0;
+    int64_t nfull = 0;
+    if (n64 > 0) {
+        // the FP64 rule over each point's candidates
+        IFGP_TRY(ensure(L.ncand, sizeof(int32_t) * (size_t)n64, s));
+        IFGP_TRY(ensure(L.cand, sizeof(Cand) * (size_t)(n64 * LABEL_CAND), s));
+        int32_t *ncand = L.ncand.as<int32_t>();
+        Cand *cand = L.cand.as<Cand>();
+        label_fill_kernel<int32_t><<<grid_for(ceil_div(n64, (int64_t)256)), 256, 0, s>>>(ncand, n64, 0);
+        label_fill_kernel<int32_t><<<1, 64, 0, s>>>(cnt, 1, 0);  // the full list reuses list32
+        IFGP_LAUNCHED();
+        int64_t chunks = 0, cpc = 0;
+        const int64_t groups = ceil_div(n64, (int64_t)16);
+        label_chunks(groups, nblk, &chunks, &cpc);
+        label_cand_kernel<Dp><<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
+            Z, d, list64, n64, thr64, L.f32.as<float>(), L.cn32.as<float>(), nid, nblk, chunks,
+            cpc, ncand, cand);
+        IFGP_LAUNCHED();
+        label_cand64_kernel<Dp><<<grid_for(ceil_div(groups, (int64_t)LW)), 64 * LW, 0, s>>>(
+            Z, d, list64, n64, thr64, ncand, cand, L.f64.as<double>(), L.cn64.as<double>(),
+            L.gidx.as<int32_t>(), best_id, best32, L.second32.as<float>(), list32, cnt);
+        IFGP_LAUNCHED();
+        IFGP_TRY(read_counts(L, s));
+        nfull = L.hcount[0];
+    }
+    if (nfull > 0) {
+        // the full FP64 pass for points with too many candidates
+        int64_t chunks = 0, cpc = 0;
+        const int64_t groups = ceil_div(nfull, (int64_t)16);
+        label_chunks(groups, nblk, &chunks, &cpc);
+        IFGP_TRY(ensure(L.part, sizeof(Part64) * (size_t)(nfull * chunks), s));
+        label_part64_kernel<Dp><<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
+            Z, d, list32, nfull, L.f64.as<double>(), L.cn64.as<double>(), L.gidx.as<int32_t>(), nid,
+            nblk, chunks, cpc, L.part.as<Part64>());
+        IFGP_LAUNCHED();
+        label_pick64_kernel<<<grid_for(ceil_div(nfull, (int64_t)256)), 256, 0, s>>>(
+            list32, nfull, chunks, L.part.as<Part64>(), best_id, best32);
+        IFGP_LAUNCHED();
+    }
+    L.last_counts[0] = n32;
+    L.last_counts[1] = n64;
+    L.last_counts[2] = up.m_pack;
+    L.last_counts[3] = nfull;
+    label_map_kernel<<<grid_for(ceil_div(n, (int64_t)256)), 256, 0, s>>>(n, best_id,
+                                                                         L.gidx.as<int32_t>(), labels);
+    IFGP_LAUNCHED();
     return IFGP_OK;
 }
 
@@ -1193,71 +1817,59 @@ IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, i
     const int d = b->d, Dp = b->Dp;
     if (n < L.n_prev) L.n_prev = 0;  // not the rows labelled before: start over
     const int64_t n_old = L.n_prev;
-    int64_t m = 0;
-    double cmax = 0.0;
+    Upload up;
     try {
-        IFGP_TRY(upload_changes(b, s, &m, &cmax));
+        IFGP_TRY(upload_changes(b, s, &up));
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return IFGP_E_OOM;
     }
     if (n > L.cap_pts) {
         const int64_t cap = std::max<int64_t>(n, L.cap_pts * 3 / 2);
-        Buf bid, b32;
+        Buf bid, b32, s32;
         IFGP_TRY(alloc(bid, sizeof(int32_t) * cap, s));
         IFGP_TRY(alloc(b32, sizeof(float) * cap, s));
+        IFGP_TRY(alloc(s32, sizeof(float) * cap, s));
         if (n_old > 0) {
             IFGP_HIP(hipMemcpyAsync(bid.p, L.best_id.p, sizeof(int32_t) * n_old, hipMemcpyDeviceToDevice, s));
             IFGP_HIP(hipMemcpyAsync(b32.p, L.best32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
+            IFGP_HIP(hipMemcpyAsync(s32.p, L.second32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
         }
-        IFGP_TRY(alloc(L.lists, sizeof(int32_t) * 2 * cap, s));
+        IFGP_TRY(alloc(L.lists, sizeof(int32_t) * 3 * cap, s));
         L.best_id = std::move(bid);
         L.best32 = std::move(b32);
+        L.second32 = std::move(s32);
         L.cap_pts = cap;
     }
     IFGP_TRY(ensure(L.counters, sizeof(int32_t) * 2, s));
-    int32_t *cnt = L.counters.as<int32_t>();
-    int32_t *list32 = L.lists.as<int32_t>(), *list64 = list32 + L.cap_pts;
-    label_fill_kernel<int32_t><<<1, 64, 0, s>>>(cnt, 2, 0);
-    IFGP_LAUNCHED();
-    // nearest entry in FP32 within 2 beta of the FP64 one: cmax bounds every |c|
-    const float cm = (float)(cmax * (1.0 + 1e-6)) + 1e-30f;
-    const int64_t nblk = ceil_div((int64_t)b->next_id, (int64_t)16);
-    const float *pf = L.cmp.as<float>();
-    const float *pcn = pf + (size_t)L.cmp_blk * 16 * Dp;
-    const int32_t *pid = reinterpret_cast<const int32_t *>(pcn + L.cmp_blk * 16);
-    const int64_t cblk = ceil_div(m, (int64_t)16);
-    const unsigned wavegrid_old = (unsigned)ceil_div(n_old, (int64_t)16 * LW);
-    const dim3 wavegrid = grid_for(ceil_div(n, (int64_t)16 * LW));
-#define IFGP_UPD(DP)                                                                              \
-    do {                                                                                          \
-        if (n_old > 0)                                                                            \
-            label_changed_kernel<DP><<<grid_for(wavegrid_old), 64 * LW, 0, s>>>(                  \
-                Z, n_old, d, pf, pcn, pid, cblk, L.chg.as<uint8_t>(), cm, L.best_id.as<int32_t>(), \
-                L.best32.as<float>(), list32, cnt);                                               \
-        if (n > n_old)                                                                            \
-            label_push_kernel<<<grid_for(ceil_div(n - n_old, (int64_t)256)), 256, 0, s>>>(        \
-                n_old, n, list32, cnt);                                                           \
-        label_full32_kernel<DP><<<wavegrid, 64 * LW, 0, s>>>(                                     \
-            Z, d, list32, cnt, L.f32.as<float>(), L.cn32.as<float>(), nblk, cm,                   \
-            L.best_id.as<int32_t>(), L.best32.as<float>(), list64, cnt + 1);                      \
-        label_full64_kernel<DP><<<wavegrid, 64 * LW, 0, s>>>(                                     \
-            Z, d, list64, cnt + 1, L.f64.as<double>(), L.cn64.as<double>(), L.idx.as<int32_t>(),  \
-            nblk, (int64_t)b->next_id, L.best_id.as<int32_t>(), L.best32.as<float>());            \
-    } while (0)
+    if (!L.hcount) IFGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&L.hcount), 64, 0));
+    ifgp_status st = IFGP_OK;
     switch (Dp) {
-    case 8: IFGP_UPD(8); break;
-    case 16: IFGP_UPD(16); break;
-    case 32: IFGP_UPD(32); break;
-    case 64: IFGP_UPD(64); break;
+    case 8: st = label_passes<8>(b, Z, n, n_old, up, labels, s); break;
+    case 16: st = label_passes<16>(b, Z, n, n_old, up, labels, s); break;
+    case 32: st = label_passes<32>(b, Z, n, n_old, up, labels, s); break;
+    case 64: st = label_passes<64>(b, Z, n, n_old, up, labels, s); break;
     default: break;
     }
-#undef IFGP_UPD
-    IFGP_LAUNCHED();
-    label_map_kernel<<<grid_for(ceil_div(n, (int64_t)256)), 256, 0, s>>>(
-        n, L.best_id.as<int32_t>(), L.idx.as<int32_t>(), labels);
-    IFGP_LAUNCHED();
+    if (st != IFGP_OK) {
+        L.n_prev = 0;  // the points' state is not known: the next update starts over
+        return st;
+    }
     L.n_prev = n;
+    return IFGP_OK;
+}
+
+IFGP_API ifgp_status ifgp_birch_update_stats(ifgp_birch_t b, int64_t *new_entries,
+                                             int64_t *fp32_rows, int64_t *fp64_rows,
+                                             int64_t *fp64_full_rows) {
+    if (!b) {
+        set_error("ifgp_birch_update_stats: need a tree");
+        return IFGP_E_INVALID;
+    }
+    if (new_entries) *new_entries = b->ls.last_counts[2];
+    if (fp32_rows) *fp32_rows = b->ls.last_counts[0];
+    if (fp64_rows) *fp64_rows = b->ls.last_counts[1];
+    if (fp64_full_rows) *fp64_full_rows = b->ls.last_counts[3];
     return IFGP_OK;
 }
 

@@ -28,6 +28,13 @@ def asan_runtime() -> str:
     return hits[-1]
 
 
+def preload_with_asan() -> str:
+    """LD_PRELOAD for a sanitised child: the ASan runtime first (it must come
+    first in the library list), then whatever the environment preloads."""
+    rest = os.environ.get("LD_PRELOAD", "")
+    return asan_runtime() + (":" + rest if rest else "")
+
+
 def main(argv):
     build = "--no-build" not in argv
     args = [a for a in argv if a != "--no-build"] or ["-x", "-q", "-m", "not gpu", "tests/"]
@@ -38,8 +45,8 @@ def main(argv):
     nm = subprocess.run(["nm", "-D", b.LIB_SAN], capture_output=True, text=True).stdout
     if "__asan_report" not in nm or "__ubsan_handle" not in nm:
         raise SystemExit(f"{b.LIB_SAN} is not instrumented")
-    env = dict(os.environ, IFGP_LIBRARY=b.LIB_SAN, LD_PRELOAD=asan_runtime(),
-               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
+    env = dict(os.environ, IFGP_LIBRARY=b.LIB_SAN, LD_PRELOAD=preload_with_asan(),
+               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     print(f"sanitizer run: IFGP_LIBRARY={b.LIB_SAN}", flush=True)
     return subprocess.call([sys.executable, "-m", "pytest", *args], cwd=ROOT, env=env)

@@ -172,14 +172,56 @@ def _steps(ifgp, X, cuts, thr, B, check_every=True):
     Zt = torch.as_tensor(X, device="cuda")
     b = ifgp.Birch(X.shape[1], thr, B)
     out = torch.empty(X.shape[0], dtype=torch.int32, device="cuda")
+    stats = []
     for lo, hi in zip(cuts[:-1], cuts[1:]):
         b.partial_fit(Zt[lo:hi])
         upd = b.predict_update(Zt[:hi], out=out[:hi]).cpu().numpy()
         full = b.predict(Zt[:hi]).cpu().numpy()
         n_diff = int((upd != full).sum())
-        log(f"  rows {hi}, clusters {b.info()['clusters']}: {n_diff} labels differ")
+        st = b.update_stats()
+        stats.append(st)
+        log(f"  rows {hi}, clusters {b.info()['clusters']}: {n_diff} labels differ; "
+            f"new twin groups {st['new_entries']}, FP32 rows {st['fp32_rows']}, "
+            f"FP64 rows {st['fp64_rows']} ({st['fp64_full_rows']} against every entry)")
         assert n_diff == 0, np.flatnonzero(upd != full)[:10]
     b.destroy()
+    return stats
+
+
+@pytest.mark.parametrize("dyadic", [False, True])
+def test_label_update_twin_entries(ifgp, dyadic):
+    """Rows repeated many times (as an embedding repeats the rows of nodes
+    with equal neighbourhoods) leave twin leaf entries when copies descend to
+    different leaves, and copies absorbed later move single twins out of
+    their groups.  At every step the update path's labels equal the full
+    labelling's.  With coordinates k / 1024 (dyadic) the mean of n copies is
+    the copy itself, so twins are equal bit for bit and tie exactly;
+    otherwise a mean can round one unit in the last place away from the copy.
+    A copy lying between the entry of its pure copies and one that absorbed
+    a perturbed copy is a near tie within the FP32 bound: the FP64 rule
+    decides it over a few candidates, so the full FP64 pass stays rare."""
+    rng = np.random.default_rng(7)
+    base = rng.random((1500, 16))
+    if dyadic:
+        base = np.round(base * 1024) / 1024
+    base = base.astype(np.float32)
+    X = base[rng.integers(0, 1500, size=30000)]
+    X[::7] += (rng.normal(size=X[::7].shape) * 0.01).astype(np.float32)
+    cuts = [0, 3000, 9000, 15000, 22000, 30000]
+    log(f"label update with twin entries (dyadic {dyadic})")
+    stats = _steps(ifgp, X, cuts, 0.05, 8)
+    # the host tree alone (no device) gives the twin count of the final tree
+    b = ifgp.Birch(16, 0.05, 8)
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        b.partial_fit(X[lo:hi])
+    _, cnt = np.unique(b.centers(), axis=0, return_counts=True)
+    b.destroy()
+    twins = int(cnt[cnt > 1].sum())
+    log(f"entries in twin groups: {twins}")
+    # near ties have few candidates: the full FP64 pass stays rare
+    assert max(st["fp64_full_rows"] for st in stats) < 0.01 * X.shape[0]
+    if dyadic:
+        assert twins > 1000
 
 
 @pytest.mark.parametrize("n,d,k,thr,B,steps", [(20000, 32, 60, 0.35, 50, 6),

@@ -26,8 +26,8 @@ def san():
     if (not os.path.exists(b.LIB_SAN)
             or os.path.getmtime(b.LIB_SAN) < max(os.path.getmtime(f) for f in srcs)):
         b.build(out=b.LIB_SAN, sanitize=True)
-    env = dict(os.environ, IFGP_LIBRARY=b.LIB_SAN, LD_PRELOAD=sc.asan_runtime(),
-               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
+    env = dict(os.environ, IFGP_LIBRARY=b.LIB_SAN, LD_PRELOAD=sc.preload_with_asan(),
+               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     return env
 
