@@ -216,9 +216,13 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
     (d=32, tau=-1, K=8, BF16), partially fits BIRCH (threshold 0.5) to the
     new nodes' embeddings, keeps them, and labels every node so far
     (ifgp_birch_predict_update: old rows against the changed centroids only).
-    Per-step latency with its parts, and the full FP64 labelling of the same
-    rows timed beside it (not part of the step); every input already in
-    device memory."""
+    Per-step latency with its parts, the rows each stage of the labelling
+    took, and the full FP64 labelling of the same rows timed beside it (not
+    part of the step); every input already in device memory.  The labelling's
+    roofline at the last step counts the FP32 matrix-core work of its passes
+    (old rows x new twin groups, FP32-pass rows x clusters, FP64-rule rows x
+    clusters for their candidate search, 2 d flops each) over the whole call,
+    host upload included, against the FP32 matrix peak."""
     import torch
     from workloads import dcsbm
     say("snowball: N=200000, 10 node batches")
@@ -235,7 +239,7 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
     kept = torch.empty((g.N, d), dtype=torch.float32, device="cuda")
     labels = torch.empty(g.N, dtype=torch.int32, device="cuda")
     full = torch.empty(g.N, dtype=torch.int32, device="cuda")
-    rows = []
+    rows, stats = [], []
     for rep in range(reps + 1):
         G, b = None, ifgp.Birch(d, 0.5, 50)
         torch.cuda.synchronize()
@@ -255,6 +259,7 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
             b.predict_update(kept[:n_t], out=labels[:n_t])
             torch.cuda.synchronize()
             t3 = time.perf_counter()
+            st = b.update_stats()
             # beside the pipeline: the same labels recomputed in full (FP64)
             b.predict(kept[:n_t], out=full[:n_t])
             torch.cuda.synchronize()
@@ -263,10 +268,16 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
             if rep > 0:
                 rows.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2, b.info()["clusters"], t4 - t3,
                              float(same)))
+                if rep == 1:
+                    stats.append(dict(st, rows=n_t))
         G.destroy()
         b.destroy()
     r = np.array(rows) * np.array([1e3, 1e3, 1e3, 1e3, 1.0, 1e3, 1.0])
     per = r.reshape(reps, steps, 7).mean(axis=0)
+    last, M = stats[-1], int(per[-1, 4])
+    flops32 = 2.0 * d * (cut[-2] * last["new_entries"]
+                         + (last["fp32_rows"] + last["fp64_rows"]) * M)
+    achieved = flops32 / (per[-1, 3] * 1e-3) / 1e12
     return {"workload": "Alg. 2 snowball: DC-SBM N=200000 B=100 mean degree 20, nodes arrive in 10 "
                         "batches of 20000 (seeded order) with their edges to earlier nodes; per step "
                         "stream_add(new_N) + FFP d=32 tau=-1 K=8 bf16 + BIRCH partial fit of the new "
@@ -279,7 +290,12 @@ def bench_snowball(ifgp, say, steps=10, reps=3):
                                  "labels_device": [float(x) for x in per[:, 3]],
                                  "labels_full_fp64_for_comparison": [float(x) for x in per[:, 5]]},
             "labels_equal_full_fp64": bool(r[:, 6].min() == 1.0),
-            "clusters_final": int(per[-1, 4])}
+            "label_update_stages": stats,
+            "labels_roofline_last_step": {"bound": "mfma", "achieved": achieved, "peak": 157.3,
+                                          "unit": "TFLOP/s", "frac": achieved / 157.3,
+                                          "flops": flops32, "precision": "fp32",
+                                          "time": "whole predict_update call"},
+            "clusters_final": M}
 
 
 # The paper's embedding-phase times (Table IX, "Emb") with its settings

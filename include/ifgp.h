@@ -233,7 +233,11 @@ IFGP_API ifgp_status ifgp_plan_info(ifgp_graph_t g, int64_t *hub_rows, int64_t *
                                     int64_t *hop_blocks, int32_t *max_degree);
 
 /* Copy the CSR to host memory: rowptr N+1 entries, colidx nnz entries (ascending
- * within each row), deg N entries.  Synchronises the stream of the last call. */
+ * within each row), deg N entries.  Synchronises the stream of the last call.
+ * A fresh build leaves the canonical colidx unmade (the hop runs on the
+ * relabelled copy); the first export of colidx, or the first ifgp_stream_add,
+ * makes it on the device (4 nnz bytes) and releases the build's survivors
+ * (4 bytes per edge end), so it can fail with IFGP_E_OOM. */
 IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *colidx, int32_t *deg);
 
 /* Copy s_i = (D_tau)_ii^{-1/2} in FP64 for node i = 0 .. N-1 to host memory
@@ -241,7 +245,10 @@ IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *c
 IFGP_API ifgp_status ifgp_export_scales(ifgp_graph_t g, double tau, double eps, double *s_host);
 
 /* Device bytes a graph with N nodes and nnz stored entries needs resident for
- * embeddings of width d in `storage` (graph, scales, features, statistics). */
+ * embeddings of width d in `storage` (graph, scales, features, statistics).
+ * Until the first export or merge after a build, the graph holds 4 bytes per
+ * edge end (2E) in place of the canonical colidx's 4 nnz: pass nnz = 2E for
+ * an upper bound that also covers that state. */
 IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int32_t storage,
                                  int64_t *bytes);
 

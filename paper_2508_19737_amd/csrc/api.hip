@@ -333,6 +333,7 @@ IFGP_API ifgp_status ifgp_stream_add(ifgp_graph_t g, const int64_t *src, const i
     hipStream_t s = (hipStream_t)hip_stream;
     Edges e;
     IFGP_TRY(stage_edges(src, dst, num_edges, edges_on_device, s, e));
+    IFGP_TRY(ensure_colidx(g->g, s));
     GraphData fresh;
     IFGP_TRY(merge_graph_device(g->g, e.src, e.dst, num_edges, new_N, s, fresh));
     // commit: nothing below can fail
@@ -442,6 +443,7 @@ IFGP_API ifgp_status ifgp_export_csr(ifgp_graph_t g, int64_t *rowptr, int32_t *c
     IFGP_TRY(check_handle(g));
     IFGP_TRY(use_device(g));
     hipStream_t s = g->stream;
+    if (colidx) IFGP_TRY(ensure_colidx(g->g, s));
     const GraphData &G = g->g;
     if (rowptr)
         IFGP_HIP(hipMemcpyAsync(rowptr, G.rowptr.p, sizeof(int64_t) * (G.N + 1),
@@ -474,8 +476,11 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
         return IFGP_E_INVALID;
     }
     const int64_t Dp = padded_width(d);
-    // resident graph: canonical CSR + degrees + plan (perm, iperm, relabelled CSR)
-    int64_t total = 2 * (8 * (N + 1) + 4 * nnz) + 4 * N * 3;
+    // resident graph: canonical CSR + degrees + plan (perm, iperm, relabelled CSR);
+    // until the first export or merge after a build, the build's survivors
+    // (4 bytes per edge end, at most nnz as counted here when nnz = 2E) and
+    // bucket starts (at most 8 (N + 1)) stand in for the canonical colidx
+    int64_t total = 2 * (8 * (N + 1) + 4 * nnz) + 4 * N * 3 + 8 * (N + 1);
     // scales: FP64 s, FP32 s and (s, sqrt(D_tau), r, 0) as float4
     total += 8 * N + 4 * N + 16 * N;
     // two feature buffers, block statistics (bounded by the row classes:

@@ -436,12 +436,12 @@ __device__ __forceinline__ void scan_gpos(Lds &sh) {
 }
 
 // Survivors of the sorted local keys src[0, n) (LDS or global): the first of
-// each run of equal keys, sentinels dropped.  Their columns go to out[] in
-// order; row r of the bucket owns survivors [rstart[r], rend[r]).  Every
-// thread calls it.
+// each run of equal keys, sentinels dropped.  They go to out[] in order, as
+// local keys (row in the bucket << B | column); row r of the bucket owns
+// survivors [rstart[r], rend[r]).  Every thread calls it.
 template <typename Lds, typename P>
 __device__ __forceinline__ void bucket_survivors(Lds &sh, P src, int64_t n, int B,
-                                                 uint64_t cmask, int32_t *__restrict__ out) {
+                                                 uint32_t *__restrict__ out) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t lt = __lanemask_lt();
     int64_t kept = 0;
@@ -467,7 +467,7 @@ __device__ __forceinline__ void bucket_survivors(Lds &sh, P src, int64_t n, int 
             total += sh.wsum[ww];
         }
         const int64_t pos = kept + before + __popcll(m & lt);
-        if (keep) out[pos] = (int32_t)(k & cmask);
+        if (keep) out[pos] = k;
         if (first) sh.rstart[row] = pos;
         if (last) sh.rend[row] = pos + (keep ? 1 : 0);
         kept += total;
@@ -555,11 +555,11 @@ __global__ void bucket_big_list_kernel(const int64_t *__restrict__ bstart, int64
 
 // One block per bucket of at most BK_CAP keys (larger ones are left to
 // bucket_big_kernel): sort its keys by (row, col) in LDS, drop repeats and
-// self loops, write the surviving columns to tcol[bstart[b] ...] in order and
-// the degrees of the bucket's rows.
+// self loops, write the survivors' local keys to tcol[bstart[b] ...] in order
+// and the degrees of the bucket's rows.
 __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void bucket_csr_kernel(
     const uint64_t *__restrict__ keys, const int64_t *__restrict__ bstart, int64_t N, int B,
-    int s, int64_t nbk, int32_t *__restrict__ tcol, int32_t *__restrict__ deg,
+    int s, int64_t nbk, uint32_t *__restrict__ tcol, int32_t *__restrict__ deg,
     int64_t *__restrict__ stats) {
     __shared__ BucketLds<BK_THREADS, BK_KPL> sh;
     const int tid = threadIdx.x;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
     }
     if (rounds > 0)
         for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
-    bucket_survivors(sh, sh.a, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+    bucket_survivors(sh, sh.a, n, B, tcol + bs);
     bucket_degrees(sh, b, s, N, deg, stats);
 }
 
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
 __global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
     const uint64_t *__restrict__ keys, uint64_t *__restrict__ scratch,
     const int64_t *__restrict__ bstart, const int64_t *__restrict__ big,
-    const int64_t *__restrict__ nbig, int64_t N, int B, int s, int32_t *__restrict__ tcol,
+    const int64_t *__restrict__ nbig, int64_t N, int B, int s, uint32_t *__restrict__ tcol,
     int32_t *__restrict__ deg, int64_t *__restrict__ stats) {
     using Lds = BucketLds<BK_BIG_THREADS, BK_BIG_KPL>;
     __shared__ Lds sh;
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
             for (int i = tid; i < rounds * T; i += T)
                 sh.a[i] = i < n ? local_key(keys[bs + i], N, B, s) : BK_NONE;
             for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
-            bucket_survivors(sh, sh.a, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+            bucket_survivors(sh, sh.a, n, B, tcol + bs);
             bucket_degrees(sh, b, s, N, deg, stats);
             __syncthreads();
             continue;
@@ -657,64 +657,67 @@ __global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
             y = t;
         }
         __syncthreads();
-        bucket_survivors(sh, x, n, B, ((uint64_t)1 << B) - 1, tcol + bs);
+        bucket_survivors(sh, x, n, B, tcol + bs);
         bucket_degrees(sh, b, s, N, deg, stats);
         __syncthreads();
     }
 }
 
-// One block per bucket, after the plan: the bucket's columns (tcol, in row
-// order) become the canonical colidx, and each entry is placed in the
-// relabelled CSR: entry q of row i goes to irowptr[iperm[i]] + q, column
-// iperm[j].  The row of an entry is found by binary search over the
-// bucket's row starts, held in LDS.
+// One block per bucket, after the plan: each survivor (local key: row in the
+// bucket << B | column, in row order) is placed in the relabelled CSR: entry q
+// of row i goes to irowptr[iperm[i]] + q, column iperm[j].
 constexpr int FN_THREADS = 256;
 constexpr int FN_ITEMS = 8;  // entries per thread in flight
 __global__ __launch_bounds__(FN_THREADS) void bucket_finish_kernel(
-    const int32_t *__restrict__ tcol, const int64_t *__restrict__ bstart,
+    const uint32_t *__restrict__ tcol, const int64_t *__restrict__ bstart,
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ iperm,
-    const int64_t *__restrict__ irowptr, int64_t N, int s, int32_t *__restrict__ colidx,
+    const int64_t *__restrict__ irowptr, int64_t N, int B, int s,
     int32_t *__restrict__ icolidx) {
-    __shared__ int64_t lo[(1 << BK_SMAX) + 1];
-    __shared__ int64_t dst[1 << BK_SMAX];
+    __shared__ int64_t dst[1 << BK_SMAX];  // per row: its first place minus its first entry
     const int64_t b = block_index(), r0 = b << s;
     if (r0 >= N) return;  // also every block past the last bucket
     const int nr = (int)((N - r0) < ((int64_t)1 << s) ? (N - r0) : ((int64_t)1 << s));
-    const int64_t p0 = rowptr[r0];
-    for (int r = threadIdx.x; r <= nr; r += FN_THREADS) lo[r] = rowptr[r0 + r] - p0;
-    for (int r = threadIdx.x; r < nr; r += FN_THREADS) dst[r] = irowptr[iperm[r0 + r]];
+    const int64_t p0 = rowptr[r0], cnt = rowptr[r0 + nr] - p0;
+    for (int r = threadIdx.x; r < nr; r += FN_THREADS)
+        dst[r] = irowptr[iperm[r0 + r]] - (rowptr[r0 + r] - p0);
     __syncthreads();
-    const int64_t cnt = lo[nr];
-    const int32_t *src = tcol + bstart[b];
+    const uint32_t *src = tcol + bstart[b];
+    const uint32_t cmask = (1u << B) - 1u;
     for (int64_t q0 = 0; q0 < cnt; q0 += FN_THREADS * FN_ITEMS) {
-        int32_t j[FN_ITEMS], v[FN_ITEMS];
+        uint32_t k[FN_ITEMS];
+        int32_t v[FN_ITEMS];
 #pragma unroll
         for (int it = 0; it < FN_ITEMS; ++it) {
             const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
-            j[it] = q < cnt ? src[q] : 0;
+            k[it] = q < cnt ? src[q] : 0u;
         }
 #pragma unroll
         for (int it = 0; it < FN_ITEMS; ++it) {
             const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
-            if (q < cnt) {
-                colidx[p0 + q] = j[it];
-                v[it] = iperm[j[it]];
-            }
+            if (q < cnt) v[it] = iperm[k[it] & cmask];
         }
 #pragma unroll
         for (int it = 0; it < FN_ITEMS; ++it) {
             const int64_t q = q0 + it * FN_THREADS + threadIdx.x;
-            if (q < cnt) {
-                int a = 0, c = nr;  // lo[a] <= q < lo[c]
-                while (c - a > 1) {
-                    const int mid = (a + c) >> 1;
-                    if (lo[mid] <= q) a = mid;
-                    else c = mid;
-                }
-                icolidx[dst[a] + (q - lo[a])] = v[it];
-            }
+            if (q < cnt) icolidx[dst[k[it] >> B] + q] = v[it];
         }
     }
+}
+
+// The canonical colidx from a build's survivors (one block per bucket): the
+// bucket's entries, in row order, from tcol[bstart[b] ...] to
+// colidx[rowptr[b << s] ...], columns only.
+__global__ void canonical_colidx_kernel(const uint32_t *__restrict__ tcol,
+                                        const int64_t *__restrict__ bstart,
+                                        const int64_t *__restrict__ rowptr, int64_t N, int B,
+                                        int s, int32_t *__restrict__ colidx) {
+    const int64_t b = block_index(), r0 = b << s;
+    if (r0 >= N) return;
+    const int64_t r1 = (N - r0) < ((int64_t)1 << s) ? N : r0 + ((int64_t)1 << s);
+    const int64_t p0 = rowptr[r0], cnt = rowptr[r1] - p0;
+    const uint32_t *src = tcol + bstart[b];
+    const uint32_t cmask = (1u << B) - 1u;
+    for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) colidx[p0 + q] = (int32_t)(src[q] & cmask);
 }
 
 inline dim3 grid1(int64_t n, int t = T256) { return grid_for(ceil_div(n, t)); }
@@ -892,11 +895,13 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
     IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted,
                             passes ? hist.as<int64_t>() : nullptr));
     uint64_t *other = sorted == keys.as<uint64_t>() ? tmp.as<uint64_t>() : keys.as<uint64_t>();
-    Buf bst, tcol;
-    IFGP_TRY(alloc(bst, sizeof(int64_t) * (nbk + 1), s));
-    IFGP_TRY(alloc(tcol, sizeof(int32_t) * n, s));
     GraphData g;
     g.N = N;
+    Buf &bst = g.bst, &tcol = g.tcol;
+    IFGP_TRY(alloc(bst, sizeof(int64_t) * (nbk + 1), s));
+    IFGP_TRY(alloc(tcol, sizeof(uint32_t) * n, s));
+    g.tcol_B = B;
+    g.tcol_s = sb;
     IFGP_TRY(alloc(g.deg, sizeof(int32_t) * N, s));
     bucket_bounds_kernel<<<grid1(nbk + 1), T256, 0, s>>>(sorted, n, B, sb, nbk,
                                                           bst.as<int64_t>());
@@ -918,12 +923,12 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
         IFGP_HIP(hipStreamWaitEvent(aux, ev_fork, 0));
     }
     bucket_big_kernel<<<(unsigned)BK_BIG_BLOCKS, BK_BIG_THREADS, 0, s>>>(
-        sorted, other, bst.as<int64_t>(), big.as<int64_t>(), nbig, N, B, sb, tcol.as<int32_t>(),
+        sorted, other, bst.as<int64_t>(), big.as<int64_t>(), nbig, N, B, sb, tcol.as<uint32_t>(),
         g.deg.as<int32_t>(), ctr.as<int64_t>() + C_MAXDEG);
     hipError_t le = hipGetLastError();
     if (le == hipSuccess) {
         bucket_csr_kernel<<<grid_for(nbk), BK_THREADS, 0, side ? aux : s>>>(
-            sorted, bst.as<int64_t>(), N, B, sb, nbk, tcol.as<int32_t>(), g.deg.as<int32_t>(),
+            sorted, bst.as<int64_t>(), N, B, sb, nbk, tcol.as<uint32_t>(), g.deg.as<int32_t>(),
             ctr.as<int64_t>() + C_MAXDEG);
         le = hipGetLastError();
     }
@@ -955,16 +960,35 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
         IFGP_TRY(read_counters(ctr.as<int64_t>(), N, s, g));
         IFGP_TRY(plan_order(B, bit_width((uint64_t)g.max_deg), s, g));
     }
-    IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * g.nnz, s));
+    // the canonical colidx waits for its first use (ensure_colidx); the
+    // survivors stay in g.tcol until then
     IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * g.nnz, s));
     if (g.nnz > 0) {
         bucket_finish_kernel<<<grid_for(nbk), FN_THREADS, 0, s>>>(
-            tcol.as<int32_t>(), bst.as<int64_t>(), g.rowptr.as<int64_t>(), g.iperm.as<int32_t>(),
-            g.irowptr.as<int64_t>(), N, sb, g.colidx.as<int32_t>(), g.icolidx.as<int32_t>());
+            tcol.as<uint32_t>(), bst.as<int64_t>(), g.rowptr.as<int64_t>(), g.iperm.as<int32_t>(),
+            g.irowptr.as<int64_t>(), N, B, sb, g.icolidx.as<int32_t>());
         IFGP_LAUNCHED();
     }
     g.dups = (E - g.self_loops) - g.nnz / 2;
     out = std::move(g);
+    return IFGP_OK;
+}
+
+ifgp_status ensure_colidx(GraphData &g, hipStream_t s) {
+    if (!g.tcol.p) return IFGP_OK;
+    Buf colidx;
+    IFGP_TRY(alloc(colidx, sizeof(int32_t) * g.nnz, s));
+    if (g.nnz > 0) {
+        canonical_colidx_kernel<<<grid_for((g.N >> g.tcol_s) + 1), T256, 0, s>>>(
+            g.tcol.as<uint32_t>(), g.bst.as<int64_t>(), g.rowptr.as<int64_t>(), g.N, g.tcol_B,
+            g.tcol_s, colidx.as<int32_t>());
+        IFGP_LAUNCHED();
+    }
+    g.colidx = std::move(colidx);
+    g.tcol.s = s;  // released after the kernel above, on its stream
+    g.bst.s = s;
+    g.tcol.reset();
+    g.bst.reset();
     return IFGP_OK;
 }
 

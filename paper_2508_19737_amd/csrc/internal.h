@@ -58,8 +58,14 @@ struct GraphData {
     int32_t max_deg = 0;
     // canonical CSR over original ids, columns ascending
     Buf rowptr;   // int64 N+1
-    Buf colidx;   // int32 nnz
+    Buf colidx;   // int32 nnz; after a fresh build, empty until ensure_colidx
     Buf deg;      // int32 N
+    // a fresh build's survivors until the canonical colidx is made: per
+    // bucket of 2^tcol_s rows, from tcol[bst[b]], local keys (row in the
+    // bucket << tcol_B | column) in row order
+    Buf tcol;     // uint32, 2E
+    Buf bst;      // int64, buckets + 1
+    int tcol_B = 0, tcol_s = 0;
     // plan: internal row k holds node perm[k]; rows sorted by degree,
     // descending (ties by id); the CSR relabelled into that order
     Buf perm;     // int32 N
@@ -138,7 +144,11 @@ void release_cached_blocks();
 ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
                                hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
                                hipEvent_t ev_join, GraphData &out);
-// Merge device edges into `in`, producing `out` (in is left unchanged).
+// Make the canonical colidx of a fresh build from its survivors, on stream s
+// (no-op once made); releases the survivors.
+ifgp_status ensure_colidx(GraphData &g, hipStream_t s);
+// Merge device edges into `in`, producing `out` (in is left unchanged; its
+// canonical colidx must be made).
 ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const int64_t *dst,
                                int64_t E, int64_t new_N, hipStream_t s, GraphData &out);
 
