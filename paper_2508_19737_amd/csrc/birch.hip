@@ -41,6 +41,7 @@ struct BNode {
     std::vector<BNode *> child;
     std::vector<int32_t> id;  // per entry: the leaf entry's identity (-1 in inner nodes); it
                               // stays with the entry when a split moves it to another leaf
+    std::vector<uint64_t> key;  // per leaf entry: twin_key of its centroid and norm
     BNode *prev_leaf = nullptr, *next_leaf = nullptr;
     int size() const { return (int)n.size(); }
 };
@@ -50,6 +51,34 @@ inline double dot(const double *a, const double *b, int d) {
     for (int k = 0; k < d; ++k) s += a[k] * b[k];
     return s;
 }
+
+// A hash of an entry's centroid and norm bits: four independent streams over
+// the coordinates (short dependency chains), then mixed.
+uint64_t twin_key(const double *c, int d, double cn) {
+    constexpr uint64_t M = 0xBF58476D1CE4E5B9ull;
+    uint64_t h[4] = {0x9E3779B97F4A7C15ull, 0xC2B2AE3D27D4EB4Full, 0x165667B19E3779F9ull,
+                     0x27D4EB2F165667C5ull};
+    int k = 0;
+    for (; k + 4 <= d; k += 4)
+        for (int j = 0; j < 4; ++j) {
+            uint64_t w;
+            std::memcpy(&w, &c[k + j], sizeof w);
+            h[j] = (h[j] ^ w) * M;
+        }
+    for (; k < d; ++k) {
+        uint64_t w;
+        std::memcpy(&w, &c[k], sizeof w);
+        h[k & 3] = (h[k & 3] ^ w) * M;
+    }
+    uint64_t w;
+    std::memcpy(&w, &cn, sizeof w);
+    uint64_t x = (h[0] ^ (h[1] << 17 | h[1] >> 47) ^ (h[2] << 31 | h[2] >> 33) ^
+                  (h[3] << 47 | h[3] >> 17) ^ w) * M;
+    x ^= x >> 31;
+    x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 29);
+}
+
 
 // c_k . p for the NB entries of one block at once (the block is NB * d
 // contiguous doubles, coordinate-major): every entry's sum runs over the
@@ -289,6 +318,7 @@ struct LabelState {
     TwinGroups twins;
     // host work arrays of an upload, kept between updates
     std::vector<const double *> h_c, h_cn;  // per identity: its centroid and norm in the tree
+    std::vector<uint64_t> h_key;            // per identity: its twin key (changed entries)
     std::vector<int32_t> h_changed, h_touched, h_orphan, h_order, h_kept;
     LabelState() = default;
     LabelState(const LabelState &) = delete;
@@ -349,6 +379,7 @@ BNode *new_node(ifgp_birch_s *t, bool leaf) {
     x->cn.reserve(t->B + 1);
     x->child.reserve(t->B + 1);
     x->id.reserve(t->B + 1);
+    x->key.reserve(t->B + 1);
     return x;
 }
 
@@ -361,11 +392,13 @@ void refresh(BNode *x, int k, int d) {
     double *blk = &x->ct[(size_t)(k / NB) * NB * d + k % NB];
     for (int j = 0; j < d; ++j) blk[(size_t)j * NB] = c[j];
     x->cn[k] = dot(c, c, d);
+    if (x->leaf) x->key[k] = twin_key(c, d, x->cn[k]);
 }
 
 void append(BNode *x, int d, int64_t n, const double *ls, double ss, BNode *child,
             int32_t id = -1) {
     x->id.push_back(id);
+    x->key.push_back(0);
     x->n.push_back(n);
     x->ls.insert(x->ls.end(), ls, ls + d);
     x->ss.push_back(ss);
@@ -709,15 +742,14 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // FP32 MFMA lane layout (checked on the device): lane l, slot r of the
 // 16 x 16 result holds D[4 (l / 16) + r][l % 16]; the operands are laid out as
 // for the FP64 instruction above.
+// (best, second, id) with dist added: selects instead of branches (a NaN
+// distance changes nothing, as fminf ignores it and the comparison fails).
 __device__ __forceinline__ void best2_insert(float dist, int32_t id, float &b, float &sc,
                                              int32_t &bi) {
-    if (dist < b) {
-        sc = b;
-        b = dist;
-        bi = id;
-    } else if (dist < sc) {
-        sc = dist;
-    }
+    const bool lt = dist < b;
+    sc = lt ? b : fminf(sc, dist);
+    bi = lt ? id : bi;
+    b = fminf(b, dist);
 }
 
 // (best, second, id) of the 16 lanes of each lane group, combined; ties put
@@ -831,16 +863,22 @@ __device__ __forceinline__ void pass32(const float (&a)[RT][S], const float *__r
         id = ids ? ids[cb * 16 + col] : (int32_t)(cb * 16 + col);
         __builtin_amdgcn_sched_barrier(0);
     };
+    // the row tiles' products interleaved (RT independent accumulations in
+    // flight), each tile's sum still over s in order
     auto step = [&](const float *bf, float nrm, int32_t id) {
+        f4_t acc[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            f4_t acc = {0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < RT; ++t) acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s], bf[s], acc, 0, 0, 0);
+        for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) best2_insert(nrm - 2.f * acc[r], id, b[t][r], sc[t][r], bi[t][r]);
-        }
+            for (int t = 0; t < RT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s], bf[s], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                best2_insert(nrm - 2.f * acc[t][r], id, b[t][r], sc[t][r], bi[t][r]);
     };
     load(bA, nA, iA, cb0);
     for (int64_t cb = cb0; cb < cb1; cb += 2) {
@@ -852,19 +890,20 @@ __device__ __forceinline__ void pass32(const float (&a)[RT][S], const float *__r
 }
 
 // Points rows[q] (q if rows is null), q < count, 16 RT per wave, against one
-// chunk of cpc entry blocks each (cpc even): wave w takes row group
-// w / chunks and blocks [cpc (w % chunks), ...) below nblk, and writes each
-// point's Part32 of that chunk to part[q * chunks + w % chunks].
+// chunk of cpc entry blocks each (cpc even): wave w takes chunk ch =
+// w / groups (blocks [cpc ch, ...) below nblk) and row group w % groups, and
+// writes each point's Part32 of that chunk to part[q * chunks + ch].  Waves
+// that run together share a chunk, which the XCD's L2 then holds for all.
 template <int Dp, int RT>
 __global__ __launch_bounds__(64 * LW) void label_part32_kernel(
     const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
     const float *__restrict__ F, const float *__restrict__ cn, const int32_t *__restrict__ ids,
-    int64_t nblk, int64_t chunks, int64_t cpc, Part32 *__restrict__ part) {
+    int64_t nblk, int64_t groups, int64_t chunks, int64_t cpc, Part32 *__restrict__ part) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int64_t w = block_index() * LW + (threadIdx.x >> 6);
-    const int64_t ch = w % chunks, q0 = (w / chunks) * 16 * RT;
-    if (q0 >= count) return;
+    const int64_t ch = w / groups, q0 = (w % groups) * 16 * RT;
+    if (ch >= chunks || q0 >= count) return;
     float a[RT][S];
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -989,20 +1028,20 @@ struct Cand {
 };
 
 // Points rows[q], q < count, 16 per wave, against one chunk of cpc slot
-// blocks each in FP32 (representatives only; wave w takes row group
-// w / chunks, chunk w % chunks): every entry (slot below nid) at most thr[q]
-// away is counted in ncand[q], and the first LABEL_CAND are kept in cand[q].
+// blocks each in FP32 (representatives only; wave w takes chunk w / groups,
+// row group w % groups): every entry (slot below nid) at most thr[q] away is
+// counted in ncand[q], and the first LABEL_CAND are kept in cand[q].
 template <int Dp>
 __global__ __launch_bounds__(64 * LW) void label_cand_kernel(
     const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
     const float *__restrict__ thr, const float *__restrict__ F, const float *__restrict__ cn,
-    int64_t nid, int64_t nblk, int64_t chunks, int64_t cpc, int32_t *__restrict__ ncand,
-    Cand *__restrict__ cand) {
+    int64_t nid, int64_t nblk, int64_t groups, int64_t chunks, int64_t cpc,
+    int32_t *__restrict__ ncand, Cand *__restrict__ cand) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int64_t w = block_index() * LW + (threadIdx.x >> 6);
-    const int64_t ch = w % chunks, q0 = (w / chunks) * 16;
-    if (q0 >= count) return;
+    const int64_t ch = w / groups, q0 = (w % groups) * 16;
+    if (ch >= chunks || q0 >= count) return;
     float a[S];
     load_row<S>(Z, d, q0 + col < count ? rows[q0 + col] : -1, grp, a);
     float t[4];
@@ -1105,18 +1144,19 @@ __global__ __launch_bounds__(64 * LW) void label_cand64_kernel(
 // Points rows[q], q < count, 16 per wave, against one chunk of cpc slot
 // blocks each in FP64, as the FP64 kernel compares them (nearest, then first
 // in leaf order; a twin group's members share its first entry's index gx):
-// wave w takes row group w / chunks and blocks [cpc (w % chunks), ...) below
-// nblk.
+// wave w takes chunk ch = w / groups (blocks [cpc ch, ...) below nblk) and row
+// group w % groups.
 template <int Dp>
 __global__ __launch_bounds__(64 * LW) void label_part64_kernel(
     const float *__restrict__ Z, int d, const int32_t *__restrict__ rows, int64_t count,
     const double *__restrict__ F, const double *__restrict__ cn, const int32_t *__restrict__ gidx,
-    int64_t nid, int64_t nblk, int64_t chunks, int64_t cpc, Part64 *__restrict__ part) {
+    int64_t nid, int64_t nblk, int64_t groups, int64_t chunks, int64_t cpc,
+    Part64 *__restrict__ part) {
     constexpr int S = Dp / 4;
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int64_t w = block_index() * LW + (threadIdx.x >> 6);
-    const int64_t ch = w % chunks, q0 = (w / chunks) * 16;
-    if (q0 >= count) return;
+    const int64_t ch = w / groups, q0 = (w % groups) * 16;
+    if (ch >= chunks || q0 >= count) return;
     const int64_t p = q0 + col < count ? rows[q0 + col] : -1;
     double a[S];
 #pragma unroll
@@ -1283,17 +1323,6 @@ ifgp_status ensure_slots(ifgp_birch_s *b, int64_t nblk, hipStream_t s) {
     return IFGP_OK;
 }
 
-uint64_t twin_key(const double *c, int d, double cn) {
-    uint64_t h = 0x9E3779B97F4A7C15ull;
-    for (int k = 0; k <= d; ++k) {
-        uint64_t w;
-        std::memcpy(&w, k < d ? &c[k] : &cn, sizeof w);
-        h = (h ^ w) * 0xBF58476D1CE4E5B9ull;
-        h ^= h >> 31;
-    }
-    return h;
-}
-
 // What an upload sent: m entries, the first m_pack of them new in this update
 // (twin groups none of whose members was there before) and packed for the
 // pass over old points; the largest centroid norm.
@@ -1319,6 +1348,7 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     const size_t o_c0 = (o_chg + (size_t)nid + 7) / 8 * 8;
     L.h_c.resize((size_t)nid);
     L.h_cn.resize((size_t)nid);
+    L.h_key.resize((size_t)nid);
     std::vector<int32_t> idx((size_t)nid);
     double mx = 0.0;
     int64_t k = 0;
@@ -1329,6 +1359,7 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
             L.h_c[id] = &l->c[(size_t)e * d];
             L.h_cn[id] = &l->cn[e];
             mx = std::max(mx, l->cn[e]);
+            if (all || b->chg[(size_t)id]) L.h_key[id] = l->key[e];
         }
     std::vector<int32_t> &changed = L.h_changed;
     if (all) {
@@ -1369,7 +1400,7 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     for (int32_t id : changed) {
         const double *c = L.h_c[id];
         const double cn = *L.h_cn[id];
-        const uint64_t key = twin_key(c, d, cn);
+        const uint64_t key = L.h_key[id];
         int32_t gi = -1;
         if (!T.hgrp.empty()) {
             const size_t mask = T.hgrp.size() - 1;
@@ -1539,7 +1570,8 @@ ifgp_status label_passes(ifgp_birch_s *b, const float *Z, int64_t n, int64_t n_o
             const int32_t *pid = reinterpret_cast<const int32_t *>(pcn + L.cmp_blk * 16);
             label_part32_kernel<Dp, LABEL_RT>
                 <<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
-                    Z, d, nullptr, n_old, pf, pcn, pid, pblk, chunks, cpc, L.part.as<Part32>());
+                    Z, d, nullptr, n_old, pf, pcn, pid, pblk, groups, chunks, cpc,
+                    L.part.as<Part32>());
             IFGP_LAUNCHED();
         }
         label_pick_changed_kernel<<<grid_for(ceil_div(n_old, (int64_t)256)), 256, 0, s>>>(
@@ -1561,8 +1593,8 @@ ifgp_status label_passes(ifgp_birch_s *b, const float *Z, int64_t n, int64_t n_o
         IFGP_TRY(ensure(L.part, sizeof(Part32) * (size_t)(n32 * chunks), s));
         label_part32_kernel<Dp, LABEL_RT>
             <<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
-                Z, d, list32, n32, L.f32.as<float>(), L.cn32.as<float>(), nullptr, nblk, chunks,
-                cpc, L.part.as<Part32>());
+                Z, d, list32, n32, L.f32.as<float>(), L.cn32.as<float>(), nullptr, nblk, groups,
+                chunks, cpc, L.part.as<Part32>());
         IFGP_LAUNCHED();
         label_pick32_kernel<<<grid_for(ceil_div(n32, (int64_t)256)), 256, 0, s>>>(
             Z, d, list32, n32, chunks, L.part.as<Part32>(), cm, best_id, best32,
@@ -1585,8 +1617,8 @@ ifgp_status label_passes(ifgp_birch_s *b, const float *Z, int64_t n, int64_t n_o
         const int64_t groups = ceil_div(n64, (int64_t)16);
         label_chunks(groups, nblk, &chunks, &cpc);
         label_cand_kernel<Dp><<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
-            Z, d, list64, n64, thr64, L.f32.as<float>(), L.cn32.as<float>(), nid, nblk, chunks,
-            cpc, ncand, cand);
+            Z, d, list64, n64, thr64, L.f32.as<float>(), L.cn32.as<float>(), nid, nblk, groups,
+            chunks, cpc, ncand, cand);
         IFGP_LAUNCHED();
         label_cand64_kernel<Dp><<<grid_for(ceil_div(groups, (int64_t)LW)), 64 * LW, 0, s>>>(
             Z, d, list64, n64, thr64, ncand, cand, L.f64.as<double>(), L.cn64.as<double>(),
@@ -1603,7 +1635,7 @@ ifgp_status label_passes(ifgp_birch_s *b, const float *Z, int64_t n, int64_t n_o
         IFGP_TRY(ensure(L.part, sizeof(Part64) * (size_t)(nfull * chunks), s));
         label_part64_kernel<Dp><<<grid_for(ceil_div(groups * chunks, (int64_t)LW)), 64 * LW, 0, s>>>(
             Z, d, list32, nfull, L.f64.as<double>(), L.cn64.as<double>(), L.gidx.as<int32_t>(), nid,
-            nblk, chunks, cpc, L.part.as<Part64>());
+            nblk, groups, chunks, cpc, L.part.as<Part64>());
         IFGP_LAUNCHED();
         label_pick64_kernel<<<grid_for(ceil_div(nfull, (int64_t)256)), 256, 0, s>>>(
             list32, nfull, chunks, L.part.as<Part64>(), best_id, best32);
