@@ -167,7 +167,9 @@ def test_streaming_gp_algorithm2(ifgp):
 def _steps(ifgp, X, cuts, thr, B, check_every=True):
     """Algorithm 2's labelling pattern: rows arrive in batches, the tree is
     partially fitted to each batch, then every row so far is labelled by the
-    update path and by the full FP64 kernel, which must agree exactly."""
+    update path and by the full FP64 kernel, which must agree exactly; the
+    update path's labels are also checked against the oracle's argmin over
+    the tree's centroids (equal, or a tie to rounding)."""
     import torch
     Zt = torch.as_tensor(X, device="cuda")
     b = ifgp.Birch(X.shape[1], thr, B)
@@ -178,6 +180,7 @@ def _steps(ifgp, X, cuts, thr, B, check_every=True):
         upd = b.predict_update(Zt[:hi], out=out[:hi]).cpu().numpy()
         full = b.predict(Zt[:hi]).cpu().numpy()
         n_diff = int((upd != full).sum())
+        check_labels(X[:hi].astype(np.float64), b.centers(), upd)
         st = b.update_stats()
         stats.append(st)
         log(f"  rows {hi}, clusters {b.info()['clusters']}: {n_diff} labels differ; "
@@ -311,4 +314,5 @@ def test_label_update_ties_within_one_lane(ifgp):
     upd = b.predict_update(Z).cpu().numpy()
     full = b.predict(Z).cpu().numpy()
     assert np.array_equal(upd, full), np.flatnonzero(upd != full)[:10]
+    check_labels(X, C, upd)
     b.destroy()
