@@ -187,6 +187,11 @@ def _steps(ifgp, X, cuts, thr, B, check_every=True):
             f"new twin groups {st['new_entries']}, FP32 rows {st['fp32_rows']}, "
             f"FP64 rows {st['fp64_rows']} ({st['fp64_full_rows']} against every entry)")
         assert n_diff == 0, np.flatnonzero(upd != full)[:10]
+    # a call with the tree unchanged since the last: nothing new to compare,
+    # the same labels
+    again = b.predict_update(Zt[:cuts[-1]], out=out[:cuts[-1]]).cpu().numpy()
+    assert np.array_equal(again, b.predict(Zt[:cuts[-1]]).cpu().numpy())
+    assert b.update_stats()["new_entries"] == 0
     b.destroy()
     return stats
 
