@@ -40,6 +40,11 @@ SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all",
             "-Xarch_host", "-g"]
 LIB_SAN = os.path.join(HERE, "libifgp_san.so")
+# UndefinedBehaviorSanitizer alone (no shadow memory: usable where ASan's
+# address-space reservations are not, e.g. next to the GPU runtime)
+UBSAN = ["-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+         "-Xarch_host", "-g"]
+LIB_UBSAN = os.path.join(HERE, "libifgp_ubsan.so")
 
 
 def _compile(src: str, objdir: str = OBJDIR, defines=(), extra=()) -> str:
@@ -57,22 +62,25 @@ def _compile(src: str, objdir: str = OBJDIR, defines=(), extra=()) -> str:
     return obj
 
 
-def build(jobs: int | None = None, out: str = LIB, defines=(), sanitize: bool = False) -> str:
+def build(jobs: int | None = None, out: str = LIB, defines=(), sanitize: bool | str = False) -> str:
     """Compile and link; `defines` (NAME=VALUE) override the kernels' tuning
     constants (IFGP_HOP_UNROLL, IFGP_LIGHT_ROWS, IFGP_MED_DEGREE,
     IFGP_HUB_DEGREE).  sanitize=True builds the host code with ASan and
-    UBSan (load it with the clang ASan runtime preloaded; see
-    sanitize_check.py)."""
-    extra = SANITIZE if sanitize else []
+    UBSan (load it with the clang ASan runtime preloaded), sanitize="ub" with
+    UBSan alone (the UBSan runtime on the library path); see
+    sanitize_check.py."""
+    extra = UBSAN if sanitize == "ub" else SANITIZE if sanitize else []
+    tag = "ubsan" if sanitize == "ub" else "san"
     objdir = OBJDIR if out == LIB and not sanitize else os.path.join(
-        OBJDIR, "variant_" + ("san" if sanitize else str(abs(hash(out)))))
+        OBJDIR, "variant_" + (tag if sanitize else str(abs(hash(out)))))
     os.makedirs(objdir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir, defines, extra), SOURCES))
     tmp = out + ".tmp"
-    link_extra = (["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-                   "-shared-libsan"] if sanitize else [])
+    link_extra = (["-Xarch_host", "-fsanitize=undefined", "-shared-libsan"] if sanitize == "ub"
+                  else ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                        "-shared-libsan"] if sanitize else [])
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -88,8 +96,12 @@ if __name__ == "__main__":
     ap.add_argument("--define", action="append", default=[])
     ap.add_argument("--sanitize", action="store_true",
                     help="host code with ASan + UBSan, written to libifgp_san.so")
+    ap.add_argument("--ubsan", action="store_true",
+                    help="host code with UBSan alone, written to libifgp_ubsan.so")
     a = ap.parse_args()
     if a.sanitize:
         print(build(a.jobs, LIB_SAN, a.define, sanitize=True))
+    elif a.ubsan:
+        print(build(a.jobs, LIB_UBSAN, a.define, sanitize="ub"))
     else:
         print(build(a.jobs, os.path.abspath(a.out), a.define))
