@@ -742,13 +742,15 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // FP32 MFMA lane layout (checked on the device): lane l, slot r of the
 // 16 x 16 result holds D[4 (l / 16) + r][l % 16]; the operands are laid out as
 // for the FP64 instruction above.
-// (best, second, id) with dist added: selects instead of branches (a NaN
-// distance changes nothing, as fminf ignores it and the comparison fails).
+// (best, second, id) with dist added, b <= sc kept: the new second is the
+// median of the three (one v_med3_f32), the new best their minimum.  A NaN
+// distance (only from NaN coordinates) leaves b and bi as they were and sc at
+// one of b, sc or NaN: never above the true second, so no row is decided on
+// its account.
 __device__ __forceinline__ void best2_insert(float dist, int32_t id, float &b, float &sc,
                                              int32_t &bi) {
-    const bool lt = dist < b;
-    sc = lt ? b : fminf(sc, dist);
-    bi = lt ? id : bi;
+    bi = dist < b ? id : bi;
+    sc = __builtin_amdgcn_fmed3f(b, sc, dist);
     b = fminf(b, dist);
 }
 

@@ -235,7 +235,8 @@ def test_label_update_twin_entries(ifgp, dyadic):
 @pytest.mark.parametrize("n,d,k,thr,B,steps", [(20000, 32, 60, 0.35, 50, 6),
                                                (9000, 8, 25, 0.15, 20, 5),
                                                (6000, 64, 30, 0.6, 50, 4),
-                                               (5000, 16, 20, 0.25, 7, 8)])
+                                               (5000, 16, 20, 0.25, 7, 8),
+                                               (4001, 20, 15, 0.3, 11, 3)])
 def test_label_update_equals_full_labelling(ifgp, n, d, k, thr, B, steps):
     rng = np.random.default_rng(n + d)
     c = rng.random((k, d))
@@ -258,6 +259,32 @@ def test_label_update_exact_ties(ifgp):
     more = (rng.random((500, d)) * 2 - 1).astype(np.float32)
     X = np.concatenate([left, right, mid, more])
     _steps(ifgp, X, [0, 80, 380, 600, 880], 0.05, 10)
+
+
+@pytest.mark.parametrize("d,full", [(8, True), (4, False)])
+def test_label_update_many_equidistant_entries(ifgp, d, full):
+    """Entries at +-e_k are all at the same distance from the origin: 2d
+    candidates within the FP32 bound.  With 16 (d = 8) the rows at the origin
+    take the full FP64 pass, with 8 (d = 4, the most the candidate stage
+    keeps) the FP64 rule over candidates; either way the first entry in leaf
+    order, as in the full FP64 labelling."""
+    import torch
+    rng = np.random.default_rng(d)
+    E = np.concatenate([np.eye(d), -np.eye(d)]).astype(np.float32)
+    b = ifgp.Birch(d, 0.01, 50).partial_fit(E)
+    assert b.info()["clusters"] == 2 * d
+    Z = np.concatenate([E, np.zeros((37, d), np.float32),
+                        (rng.random((200, d)) * 2 - 1).astype(np.float32)])
+    Zt = torch.as_tensor(Z, device="cuda")
+    upd = b.predict_update(Zt).cpu().numpy()
+    full_labels = b.predict(Zt).cpu().numpy()
+    st = b.update_stats()
+    log(f"+-e_k, d={d}: {st}")
+    assert np.array_equal(upd, full_labels)
+    check_labels(Z.astype(np.float64), b.centers(), upd)
+    assert st["fp64_rows"] >= 37
+    assert (st["fp64_full_rows"] >= 37) == full
+    b.destroy()
 
 
 def test_label_update_on_ffp_embedding_snowball(ifgp):
