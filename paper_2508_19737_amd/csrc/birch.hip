@@ -317,8 +317,9 @@ struct LabelState {
                                             // points left to the full FP64 pass
     TwinGroups twins;
     // host work arrays of an upload, kept between updates
-    std::vector<const double *> h_c, h_cn;  // per identity: its centroid and norm in the tree
-    std::vector<uint64_t> h_key;            // per identity: its twin key (changed entries)
+    std::vector<int32_t> h_idx;             // per identity: its leaf-order index
+    std::vector<const BNode *> h_leaf;      // per leaf-order index: the leaf holding the entry
+    std::vector<int32_t> h_pos;             // ... and its position there
     std::vector<int32_t> h_changed, h_touched, h_orphan, h_order, h_kept;
     LabelState() = default;
     LabelState(const LabelState &) = delete;
@@ -1348,21 +1349,29 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     const bool all = !L.slots_valid;
     const size_t o_chg = sizeof(int32_t) * (size_t)nid;
     const size_t o_c0 = (o_chg + (size_t)nid + 7) / 8 * 8;
-    L.h_c.resize((size_t)nid);
-    L.h_cn.resize((size_t)nid);
-    L.h_key.resize((size_t)nid);
-    std::vector<int32_t> idx((size_t)nid);
+    // leaf-order index per identity; the entry behind each index (written in
+    // leaf order), read back only for the entries that need their centroid
+    std::vector<int32_t> &idx = L.h_idx;
+    idx.resize((size_t)nid);
+    L.h_leaf.resize((size_t)nid);
+    L.h_pos.resize((size_t)nid);
     double mx = 0.0;
     int64_t k = 0;
     for (const BNode *l = b->first_leaf; l; l = l->next_leaf)
         for (int e = 0; e < l->size(); ++e, ++k) {
-            const int32_t id = l->id[e];
-            idx[id] = (int32_t)k;
-            L.h_c[id] = &l->c[(size_t)e * d];
-            L.h_cn[id] = &l->cn[e];
+            idx[l->id[e]] = (int32_t)k;
+            L.h_leaf[k] = l;
+            L.h_pos[k] = e;
             mx = std::max(mx, l->cn[e]);
-            if (all || b->chg[(size_t)id]) L.h_key[id] = l->key[e];
         }
+    struct At {
+        const BNode *leaf;
+        int e;
+    };
+    auto at = [&](int32_t id) {
+        const int32_t q = idx[id];
+        return At{L.h_leaf[q], L.h_pos[q]};
+    };
     std::vector<int32_t> &changed = L.h_changed;
     if (all) {
         T.clear();
@@ -1400,23 +1409,24 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     std::vector<int32_t> &touched = L.h_touched;
     touched.clear();
     for (int32_t id : changed) {
-        const double *c = L.h_c[id];
-        const double cn = *L.h_cn[id];
-        const uint64_t key = L.h_key[id];
+        const At a = at(id);
+        const double *c = &a.leaf->c[(size_t)a.e * d];
+        const double cn = a.leaf->cn[a.e];
+        const uint64_t kid = a.leaf->key[a.e];
         int32_t gi = -1;
         if (!T.hgrp.empty()) {
             const size_t mask = T.hgrp.size() - 1;
-            for (size_t i = key & mask; T.hgrp[i] >= 0; i = (i + 1) & mask) {
-                if (T.hkey[i] != key) continue;
-                const int32_t o = T.g[T.hgrp[i]].head;
-                if (std::memcmp(L.h_cn[o], &cn, sizeof cn) == 0 &&
-                    std::memcmp(L.h_c[o], c, sizeof(double) * d) == 0) {
+            for (size_t i = kid & mask; T.hgrp[i] >= 0; i = (i + 1) & mask) {
+                if (T.hkey[i] != kid) continue;
+                const At o = at(T.g[T.hgrp[i]].head);
+                if (std::memcmp(&o.leaf->cn[o.e], &cn, sizeof cn) == 0 &&
+                    std::memcmp(&o.leaf->c[(size_t)o.e * d], c, sizeof(double) * d) == 0) {
                     gi = T.hgrp[i];
                     break;
                 }
             }
         }
-        if (gi < 0) gi = T.make(key);
+        if (gi < 0) gi = T.make(kid);
         T.add(gi, id);
         if (T.g[gi].fresh++ == 0) touched.push_back(gi);
     }
@@ -1485,8 +1495,9 @@ ifgp_status upload_changes(ifgp_birch_s *b, hipStream_t s, Upload *up) {
     for (int32_t id : L.h_kept) chg[id] = 2;
     for (int64_t q = 0; q < m; ++q) {
         const int32_t id = order[q];
-        std::memcpy(c + (size_t)q * d, L.h_c[id], sizeof(double) * d);
-        nrm[q] = *L.h_cn[id];
+        const At a = at(id);
+        std::memcpy(c + (size_t)q * d, &a.leaf->c[(size_t)a.e * d], sizeof(double) * d);
+        nrm[q] = a.leaf->cn[a.e];
         ids[q] = id;
         rep[q] = T.g[T.of[id]].rep == id ? 1 : 0;
     }
