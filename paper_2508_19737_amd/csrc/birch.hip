@@ -53,11 +53,12 @@ inline double dot(const double *a, const double *b, int d) {
 }
 
 // A hash of an entry's centroid and norm bits: four independent streams over
-// the coordinates (short dependency chains), then mixed.
+// the coordinates (short dependency chains), then mixed as in the splitmix64
+// finaliser (Steele, Lea & Flood 2014).  Equal keys are only candidates: a
+// lookup compares the bits themselves.
 uint64_t twin_key(const double *c, int d, double cn) {
-    constexpr uint64_t M = 0xBF58476D1CE4E5B9ull;
-    uint64_t h[4] = {0x9E3779B97F4A7C15ull, 0xC2B2AE3D27D4EB4Full, 0x165667B19E3779F9ull,
-                     0x27D4EB2F165667C5ull};
+    constexpr uint64_t M = 0xBF58476D1CE4E5B9ull, G = 0x9E3779B97F4A7C15ull;
+    uint64_t h[4] = {G, 2 * G + 1, 3 * G, 4 * G + 1};
     int k = 0;
     for (; k + 4 <= d; k += 4)
         for (int j = 0; j < 4; ++j) {
@@ -716,7 +717,10 @@ ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
 // values the FP64 kernel would compare (beta below).  A point's nearest entry
 // is decided in FP32 when the runner-up is more than 2 beta further away:
 // then the FP64 order is the same.  Otherwise (ties, near ties) the point is
-// labelled by the FP64 kernel's rule, first index in leaf order on ties.
+// labelled by the FP64 kernel's rule, first index in leaf order on ties, over
+// its candidates: the entries within 2 beta of the FP32 nearest in FP32 (no
+// other entry can be nearer in FP64), or over every entry when there are more
+// than LABEL_CAND of them.
 //
 // Twin entries (centroid and norm equal bit for bit) tie exactly for every
 // point; the FP32 passes see one of each twin group, and a point that ends
@@ -727,8 +731,11 @@ ifgp_status upload_centers(ifgp_birch_s *t, hipStream_t s) {
 // A point labelled before whose nearest entry did not change keeps it against
 // every centroid that was there before (they and the point are as they were),
 // so it is compared only with the twin groups new since the last update,
-// under the same rule; a point whose nearest entry changed, or that was
-// decided in FP64, is labelled again from scratch.
+// under the same rule.  Each point also keeps a lower bound on its FP32
+// distance to every other group, so a point whose nearest entry moved is
+// settled against the new groups and that bound.  A point is labelled again
+// from scratch only when its FP32 distances are unknown (it went through the
+// full FP64 pass) or its old centroid survives in unchanged twins.
 //
 // Each pass gives a wave 64 points (four row tiles sharing every centroid
 // block it loads) and one chunk of the entry blocks, sized so that a pass
@@ -743,6 +750,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // FP32 MFMA lane layout (checked on the device): lane l, slot r of the
 // 16 x 16 result holds D[4 (l / 16) + r][l % 16]; the operands are laid out as
 // for the FP64 instruction above.
+
 // (best, second, id) with dist added, b <= sc kept: the new second is the
 // median of the three (one v_med3_f32), the new best their minimum.  A NaN
 // distance (only from NaN coordinates) leaves b and bi as they were and sc at
