@@ -94,131 +94,6 @@ __global__ __launch_bounds__(T256) void ingest_kernel(const int64_t *__restrict_
     }
 }
 
-// Deduplication of sorted keys in tiles of UQ_ITEMS consecutive keys per
-// thread: key i is kept iff it differs from key i-1 and its row is < N (self
-// loops and padding carry row N).
-constexpr int UQ_ITEMS = 8;
-constexpr int UQ_TILE = T256 * UQ_ITEMS;
-
-__device__ __forceinline__ bool keep_key(const uint64_t *__restrict__ k, int64_t i, int B,
-                                         int64_t N) {
-    const uint64_t x = k[i];
-    return (i == 0 || k[i - 1] != x) && (int64_t)(x >> B) < N;
-}
-
-// Tile t holds keys [t*UQ_TILE, (t+1)*UQ_TILE); round q of the tile gives
-// thread j key t*UQ_TILE + q*T256 + j, so loads and stores are coalesced.
-__global__ __launch_bounds__(T256) void unique_count_kernel(const uint64_t *__restrict__ k,
-                                                            int64_t n, int B, int64_t N,
-                                                            int64_t *__restrict__ bcount) {
-    const int64_t blk = block_index();
-    if (blk * UQ_TILE >= n) return;  // past the last tile
-    const int64_t base = blk * UQ_TILE + threadIdx.x;
-    int64_t c = 0;
-#pragma unroll
-    for (int q = 0; q < UQ_ITEMS; ++q) {
-        const int64_t i = base + (int64_t)q * T256;
-        if (i < n && keep_key(k, i, B, N)) ++c;
-    }
-    c = block_sum_i64(c);
-    if (threadIdx.x == 0) bcount[blk] = c;
-}
-
-__global__ __launch_bounds__(T256) void unique_write_kernel(const uint64_t *__restrict__ k,
-                                                            int64_t n, int B, int64_t N,
-                                                            const int64_t *__restrict__ boff,
-                                                            uint64_t *__restrict__ out) {
-    __shared__ int wcount[UQ_ITEMS][T256 / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t blk = block_index();
-    if (blk * UQ_TILE >= n) return;  // past the last tile
-    const int64_t base = blk * UQ_TILE + threadIdx.x;
-    const uint64_t lt = __lanemask_lt();
-    bool keep[UQ_ITEMS];
-    uint64_t key[UQ_ITEMS];
-    int below[UQ_ITEMS];
-#pragma unroll
-    for (int q = 0; q < UQ_ITEMS; ++q) {
-        const int64_t i = base + (int64_t)q * T256;
-        keep[q] = i < n && keep_key(k, i, B, N);
-        key[q] = keep[q] ? k[i] : 0;
-        const uint64_t m = __ballot(keep[q]);
-        below[q] = __popcll(m & lt);
-        if (lane == 0) wcount[q][w] = __popcll(m);
-    }
-    __syncthreads();
-    // kept keys before (round q, wave w): all earlier rounds, then earlier waves
-    int64_t pos = boff[blk];
-#pragma unroll
-    for (int q = 0; q < UQ_ITEMS; ++q) {
-        int before = 0, round = 0;
-#pragma unroll
-        for (int ww = 0; ww < T256 / 64; ++ww) {
-            before += ww < w ? wcount[q][ww] : 0;
-            round += wcount[q][ww];
-        }
-        if (keep[q]) out[pos + before + below[q]] = key[q];
-        pos += round;
-    }
-}
-
-// rowptr[r] = first index p with ukeys[p] >= (r << B), r = 0..N
-__global__ void rowptr_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
-                              int B, int64_t N, int64_t *__restrict__ rowptr) {
-    const int64_t r = block_index() * blockDim.x + threadIdx.x;
-    if (r > N) return;
-    const uint64_t target = (uint64_t)r << B;
-    int64_t lo = 0, hi = *nnz_d;
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (uk[mid] < target) lo = mid + 1;
-        else hi = mid;
-    }
-    rowptr[r] = lo;
-}
-
-__global__ void colidx_kernel(const uint64_t *__restrict__ uk, const int64_t *__restrict__ nnz_d,
-                              int64_t bound, uint64_t mask, int32_t *__restrict__ colidx) {
-    const int64_t p = block_index() * blockDim.x + threadIdx.x;
-    if (p < bound && p < *nnz_d) colidx[p] = (int32_t)(uk[p] & mask);
-}
-
-// deg and the statistics the plan needs: stats[0] = max degree,
-// stats[1] = rows with deg >= HUB_DEGREE, stats[2] = rows with deg >= MED_DEGREE.
-// Grid-stride over rows, so that few blocks meet at the atomics.
-__global__ __launch_bounds__(T256) void degree_kernel(const int64_t *__restrict__ rowptr,
-                                                      int64_t N, int32_t *__restrict__ deg,
-                                                      int64_t *__restrict__ stats) {
-    int64_t mx = 0, hub = 0, med = 0;
-    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * T256) {
-        const int64_t dg = rowptr[i + 1] - rowptr[i];
-        deg[i] = (int32_t)dg;
-        mx = dg > mx ? dg : mx;
-        hub += dg >= HUB_DEGREE;
-        med += dg >= MED_DEGREE;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const int64_t o = __shfl_xor(mx, off, 64);
-        mx = o > mx ? o : mx;
-    }
-    __shared__ int64_t red[T256 / 64];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    mx = red[0];
-#pragma unroll
-    for (int i = 1; i < T256 / 64; ++i) mx = red[i] > mx ? red[i] : mx;
-    __syncthreads();
-    hub = block_sum_i64(hub);
-    med = block_sum_i64(med);
-    if (threadIdx.x == 0) {
-        atomicMax((unsigned long long *)&stats[0], (unsigned long long)mx);
-        if (hub) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)hub);
-        if (med) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)med);
-    }
-}
-
 // key = (top - deg) << B | node with top >= every degree: ascending key =
 // descending degree, ties by id
 __global__ void order_keys_kernel(const int32_t *__restrict__ deg, int64_t N, int32_t top, int B,
@@ -238,23 +113,6 @@ __global__ void perm_kernel(const uint64_t *__restrict__ keys, int64_t N, uint64
     ideg[k] = deg[node];
 }
 
-// One thread per stored entry p of the canonical CSR (unique key (i, j)):
-// its place in the relabelled CSR is irowptr[iperm[i]] + (p - rowptr[i]) and
-// its column becomes iperm[j].  Entries are independent, so many lookups are
-// in flight at once.
-__global__ void relabel_kernel(const uint64_t *__restrict__ uk, int64_t nnz, int B,
-                               const int64_t *__restrict__ rowptr,
-                               const int32_t *__restrict__ iperm,
-                               const int64_t *__restrict__ irowptr,
-                               int32_t *__restrict__ icolidx) {
-    const int64_t p = block_index() * blockDim.x + threadIdx.x;
-    if (p >= nnz) return;
-    const uint64_t key = uk[p];
-    const int64_t i = (int64_t)(key >> B);
-    const int64_t j = (int64_t)(key & (((uint64_t)1 << B) - 1));
-    icolidx[irowptr[iperm[i]] + (p - rowptr[i])] = iperm[j];
-}
-
 // keys of a canonical CSR, packed with B bits per id: (row << B) | col
 __global__ __launch_bounds__(T256) void csr_keys_kernel(const int64_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ colidx,
@@ -265,41 +123,6 @@ __global__ __launch_bounds__(T256) void csr_keys_kernel(const int64_t *__restric
     if (r >= N) return;
     for (int64_t t = rowptr[r] + l; t < rowptr[r + 1]; t += 16)
         keys[t] = ((uint64_t)r << B) | (uint64_t)(uint32_t)colidx[t];
-}
-
-// Stable merge by rank: a[i] goes to i + #{b < a[i]}, b[j] to j + #{a <= b[j]}.
-// b holds *nb_d valid keys out of nb_bound; output slots past na + *nb_d get
-// the sentinel, so the whole output stays sorted.
-__global__ void merge_rank_kernel(const uint64_t *__restrict__ a, int64_t na,
-                                  const uint64_t *__restrict__ b, const int64_t *__restrict__ nb_d,
-                                  int64_t nb_bound, uint64_t sentinel,
-                                  uint64_t *__restrict__ out) {
-    const int64_t t = block_index() * blockDim.x + threadIdx.x;
-    const int64_t nb = *nb_d;
-    if (t < na) {
-        const uint64_t x = a[t];
-        int64_t lo = 0, hi = nb;
-        while (lo < hi) {
-            const int64_t mid = lo + ((hi - lo) >> 1);
-            if (b[mid] < x) lo = mid + 1;
-            else hi = mid;
-        }
-        out[t + lo] = x;
-    } else if (t < na + nb_bound) {
-        const int64_t j = t - na;
-        if (j < nb) {
-            const uint64_t x = b[j];
-            int64_t lo = 0, hi = na;
-            while (lo < hi) {
-                const int64_t mid = lo + ((hi - lo) >> 1);
-                if (a[mid] <= x) lo = mid + 1;
-                else hi = mid;
-            }
-            out[j + lo] = x;
-        } else {
-            out[t] = sentinel;
-        }
-    }
 }
 
 // ---------------------------------------------------------------- bucketed build
@@ -502,7 +325,8 @@ __device__ __forceinline__ uint32_t local_key(uint64_t k, int64_t N, int B, int 
 }
 
 // Degrees of bucket b's rows from sh.rstart/rend, and the block's part of
-// the statistics (as in degree_kernel).  Every thread calls it.
+// the statistics: the largest degree and the counts of hub and medium rows
+// (summed into stats[0..2] by atomics).  Every thread calls it.
 template <typename Lds>
 __device__ __forceinline__ void bucket_degrees(Lds &sh, int64_t b, int s, int64_t N,
                                                int32_t *__restrict__ deg,
@@ -740,39 +564,16 @@ ifgp_status pinned_counters(int64_t **out) {
     return IFGP_OK;
 }
 
-// Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the device.
-// Keys of E pairs -> 2E keys; self-loop pairs and bad ids counted on the
-// device; with hist, the first radix pass's tile counts of the digit at
-// hist_shift (see ingest_kernel).
-ifgp_status ingest(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
-                   hipStream_t s, Buf &keys, int64_t *ctr, int64_t *hist = nullptr,
-                   int hist_shift = 0) {
-    IFGP_TRY(alloc(keys, sizeof(uint64_t) * 2 * E, s));
+// Keys of E pairs -> 2E keys at keys[0, 2E); self-loop pairs and bad ids
+// counted on the device; with hist, the first radix pass's tile counts of the
+// digit at hist_shift (see ingest_kernel).
+ifgp_status ingest_to(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
+                      hipStream_t s, uint64_t *keys, int64_t *ctr, int64_t *hist = nullptr,
+                      int hist_shift = 0) {
     if (E > 0) {
         const int64_t ntiles = ceil_div(2 * E, (int64_t)RADIX_TILE);
         ingest_kernel<<<(unsigned)ceil_div(E, (int64_t)INGEST_EDGES), T256, 0, s>>>(
-            src, dst, E, N, B, keys.as<uint64_t>(), ctr + C_LOOPS, hist, hist_shift, ntiles);
-        IFGP_LAUNCHED();
-    }
-    return IFGP_OK;
-}
-
-// n sorted keys (repeats and sentinels allowed) -> unique keys; the count goes
-// to *nu_d on the device; uk is allocated for the upper bound n.
-ifgp_status unique_keys(const uint64_t *k, int64_t n, int B, int64_t N, hipStream_t s, Buf &uk,
-                        int64_t *nu_d) {
-    IFGP_TRY(alloc(uk, sizeof(uint64_t) * n, s));
-    const int64_t nb = ceil_div(n, UQ_TILE);
-    Buf bc;
-    IFGP_TRY(alloc(bc, sizeof(int64_t) * (nb + 1), s));
-    if (n > 0) {
-        unique_count_kernel<<<grid_for(nb), T256, 0, s>>>(k, n, B, N, bc.as<int64_t>());
-        IFGP_LAUNCHED();
-    }
-    IFGP_TRY(exclusive_scan<int64_t>(bc.as<int64_t>(), bc.as<int64_t>(), nb, nu_d, s));
-    if (n > 0) {
-        unique_write_kernel<<<grid_for(nb), T256, 0, s>>>(k, n, B, N, bc.as<int64_t>(),
-                                                          uk.as<uint64_t>());
+            src, dst, E, N, B, keys, ctr + C_LOOPS, hist, hist_shift, ntiles);
         IFGP_LAUNCHED();
     }
     return IFGP_OK;
@@ -828,39 +629,6 @@ ifgp_status plan_order(int B, int dbits, hipStream_t s, GraphData &g) {
     return IFGP_OK;
 }
 
-// Unique sorted keys (count on the device, at most bound) -> canonical CSR
-// and plan (used by the merge of stream_add).
-ifgp_status csr_and_plan(const uint64_t *uk, int64_t bound, int B, int64_t N, hipStream_t s,
-                         int64_t *ctr, GraphData &g) {
-    g.N = N;
-    IFGP_TRY(alloc(g.rowptr, sizeof(int64_t) * (N + 1), s));
-    IFGP_TRY(alloc(g.colidx, sizeof(int32_t) * bound, s));
-    IFGP_TRY(alloc(g.deg, sizeof(int32_t) * N, s));
-    rowptr_kernel<<<grid1(N + 1), T256, 0, s>>>(uk, ctr + C_NNZ, B, N, g.rowptr.as<int64_t>());
-    IFGP_LAUNCHED();
-    if (bound > 0) {
-        colidx_kernel<<<grid1(bound), T256, 0, s>>>(uk, ctr + C_NNZ, bound,
-                                                    ((uint64_t)1 << B) - 1,
-                                                    g.colidx.as<int32_t>());
-        IFGP_LAUNCHED();
-    }
-    const unsigned dgrid = (unsigned)std::min<int64_t>(ceil_div(N, T256), 1024);
-    degree_kernel<<<dgrid, T256, 0, s>>>(g.rowptr.as<int64_t>(), N, g.deg.as<int32_t>(),
-                                         ctr + C_MAXDEG);
-    IFGP_LAUNCHED();
-    IFGP_TRY(read_counters(ctr, N, s, g));
-    IFGP_TRY(plan_order(B, bit_width((uint64_t)g.max_deg), s, g));
-    const int64_t nnz = g.nnz;
-    IFGP_TRY(alloc(g.icolidx, sizeof(int32_t) * nnz, s));
-    if (nnz > 0) {
-        relabel_kernel<<<grid1(nnz), T256, 0, s>>>(uk, nnz, B, g.rowptr.as<int64_t>(),
-                                                   g.iperm.as<int32_t>(), g.irowptr.as<int64_t>(),
-                                                   g.icolidx.as<int32_t>());
-        IFGP_LAUNCHED();
-    }
-    return IFGP_OK;
-}
-
 // Rows per bucket of a fresh build: 2^s, with s as large as the 32-bit
 // local key and the row tables allow while the average bucket stays at half
 // of what one block sorts in LDS.
@@ -872,30 +640,23 @@ int bucket_bits(int64_t N, int64_t nkeys, int B) {
 
 }  // namespace
 
-ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
-                               hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
-                               hipEvent_t ev_join, GraphData &out) {
-    const int B = bit_width((uint64_t)N);  // holds 0..N (N is the sentinel row)
-    Buf ctr;
-    IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
-    IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
-    const int64_t n = 2 * E;
-    const int sb = bucket_bits(N, n, B);
-    const int64_t nbk = (N >> sb) + 1;
-    // the first radix pass's histogram is taken while the keys are made
-    Buf hist;
-    const bool passes = B + sb < 2 * B && n > 1;
-    if (passes) IFGP_TRY(alloc(hist, sizeof(int64_t) * 256 * ceil_div(n, (int64_t)RADIX_TILE), s));
-    Buf keys;
-    IFGP_TRY(ingest(src, dst, E, N, B, s, keys, ctr.as<int64_t>(),
-                    passes ? hist.as<int64_t>() : nullptr, B + sb));
+namespace {
+
+// The bucketed build from n unsorted keys (row << B | column, sentinel row N
+// allowed) in `keys`, sorted device-wide by the rows' high bits (rows per
+// bucket 2^sb) with the first pass's tile counts in hist if given; ctr holds
+// what the keys' making counted (self loops, bad ids).  Buckets sorted,
+// deduplicated and counted in LDS; rowptr, counters, plan, relabelled CSR.
+ifgp_status bucket_build(Buf &keys, int64_t n, int64_t N, int B, int sb, int64_t *hist,
+                         Buf &ctr, hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                         hipEvent_t ev_join, GraphData &g) {
     Buf tmp;
     IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
     uint64_t *sorted = nullptr;
     IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted,
-                            passes ? hist.as<int64_t>() : nullptr));
+                            hist));
     uint64_t *other = sorted == keys.as<uint64_t>() ? tmp.as<uint64_t>() : keys.as<uint64_t>();
-    GraphData g;
+    const int64_t nbk = (N >> sb) + 1;
     g.N = N;
     Buf &bst = g.bst, &tcol = g.tcol;
     IFGP_TRY(alloc(bst, sizeof(int64_t) * (nbk + 1), s));
@@ -969,6 +730,31 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
             g.irowptr.as<int64_t>(), N, B, sb, g.icolidx.as<int32_t>());
         IFGP_LAUNCHED();
     }
+    return IFGP_OK;
+}
+
+}  // namespace
+
+ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E, int64_t N,
+                               hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+                               hipEvent_t ev_join, GraphData &out) {
+    const int B = bit_width((uint64_t)N);  // holds 0..N (N is the sentinel row)
+    Buf ctr;
+    IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
+    IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
+    const int64_t n = 2 * E;
+    const int sb = bucket_bits(N, n, B);
+    // the first radix pass's histogram is taken while the keys are made
+    Buf hist;
+    const bool passes = B + sb < 2 * B && n > 1;
+    if (passes) IFGP_TRY(alloc(hist, sizeof(int64_t) * 256 * ceil_div(n, (int64_t)RADIX_TILE), s));
+    Buf keys;
+    IFGP_TRY(alloc(keys, sizeof(uint64_t) * n, s));
+    IFGP_TRY(ingest_to(src, dst, E, N, B, s, keys.as<uint64_t>(), ctr.as<int64_t>(),
+                       passes ? hist.as<int64_t>() : nullptr, B + sb));
+    GraphData g;
+    IFGP_TRY(bucket_build(keys, n, N, B, sb, passes ? hist.as<int64_t>() : nullptr, ctr, s, aux,
+                          ev_fork, ev_join, g));
     g.dups = (E - g.self_loops) - g.nnz / 2;
     out = std::move(g);
     return IFGP_OK;
@@ -995,47 +781,25 @@ ifgp_status ensure_colidx(GraphData &g, hipStream_t s) {
 ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const int64_t *dst,
                                int64_t E, int64_t new_N, hipStream_t s, GraphData &out) {
     const int B = bit_width((uint64_t)new_N);
-    Buf ctr, cinc;
+    Buf ctr;
     IFGP_TRY(alloc(ctr, sizeof(int64_t) * C_COUNT, s));
     IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
-    IFGP_TRY(alloc(cinc, sizeof(int64_t), s));
-    // increment: keys, sort, unique (count of unique increment keys in cinc)
+    // the resident entries (repacked with B bits) and the increment's keys in
+    // one array, then the bucketed build as for a fresh graph: repeats of
+    // resident edges are dropped with the other duplicates
+    const int64_t n = in.nnz + 2 * E;
+    const int sb = bucket_bits(new_N, n, B);
     Buf keys;
-    IFGP_TRY(ingest(src, dst, E, new_N, B, s, keys, ctr.as<int64_t>()));
-    Buf tmp;
-    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * 2 * E, s));
-    uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), 2 * E, 0, 2 * B, s, &sorted));
-    Buf inc;
-    IFGP_TRY(unique_keys(sorted, 2 * E, B, new_N, s, inc, cinc.as<int64_t>()));
-    keys.reset();
-    tmp.reset();
-    // resident keys repacked with B bits (row-major order is unchanged)
-    Buf res;
-    IFGP_TRY(alloc(res, sizeof(uint64_t) * in.nnz, s));
-    if (in.N > 0) {
+    IFGP_TRY(alloc(keys, sizeof(uint64_t) * n, s));
+    if (in.N > 0 && in.nnz > 0) {
         csr_keys_kernel<<<grid1(in.N, 16), T256, 0, s>>>(in.rowptr.as<int64_t>(),
                                                          in.colidx.as<int32_t>(), in.N, B,
-                                                         res.as<uint64_t>());
+                                                         keys.as<uint64_t>());
         IFGP_LAUNCHED();
     }
-    Buf merged;
-    const int64_t nm = in.nnz + 2 * E;   // upper bound; unused slots hold the sentinel
-    IFGP_TRY(alloc(merged, sizeof(uint64_t) * nm, s));
-    if (nm > 0) {
-        merge_rank_kernel<<<grid1(nm), T256, 0, s>>>(res.as<uint64_t>(), in.nnz,
-                                                     inc.as<uint64_t>(), cinc.as<int64_t>(),
-                                                     2 * E, (uint64_t)new_N << B,
-                                                     merged.as<uint64_t>());
-        IFGP_LAUNCHED();
-    }
-    res.reset();
-    inc.reset();
-    Buf uk;
-    IFGP_TRY(unique_keys(merged.as<uint64_t>(), nm, B, new_N, s, uk, ctr.as<int64_t>() + C_NNZ));
-    merged.reset();
+    IFGP_TRY(ingest_to(src, dst, E, new_N, B, s, keys.as<uint64_t>() + in.nnz, ctr.as<int64_t>()));
     GraphData g;
-    IFGP_TRY(csr_and_plan(uk.as<uint64_t>(), nm, B, new_N, s, ctr.as<int64_t>(), g));
+    IFGP_TRY(bucket_build(keys, n, new_N, B, sb, nullptr, ctr, s, nullptr, nullptr, nullptr, g));
     g.self_loops += in.self_loops;
     // pairs of this increment that added no new edge
     g.dups = in.dups + (E - (g.self_loops - in.self_loops)) - (g.nnz - in.nnz) / 2;
