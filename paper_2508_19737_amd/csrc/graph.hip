@@ -39,10 +39,11 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v) {
 }
 
 // counters[0] = self-loop pairs, counters[1] = 1 if any id is out of range.
+// Edge e's keys (edge_keys) go to keys[2e], keys[2e + 1] unless keys is null.
 // Block t takes the RADIX_TILE / 2 edges whose keys form radix tile t; with
 // hist != nullptr it also writes the tile's counts of the digit
 // (key >> hist_shift) & 255 to hist[digit * ntiles + t] (the first pass of
-// radix_sort_u64).
+// radix_sort_u64 or radix_sort_pairs).
 constexpr int INGEST_EDGES = RADIX_TILE / 2;
 __global__ __launch_bounds__(T256) void ingest_kernel(const int64_t *__restrict__ src,
                                                       const int64_t *__restrict__ dst, int64_t E,
@@ -58,21 +59,19 @@ __global__ __launch_bounds__(T256) void ingest_kernel(const int64_t *__restrict_
         __syncthreads();
     }
     int64_t loop = 0, bad = 0;
-    const uint64_t sent = (uint64_t)N << B;
 #pragma unroll 4
     for (int r = 0; r < INGEST_EDGES / T256; ++r) {
         const int64_t e = (int64_t)blockIdx.x * INGEST_EDGES + r * T256 + tid;
         if (e < E) {
             const int64_t u = src[e], v = dst[e];
-            uint64_t k0 = sent, k1 = sent;
+            uint64_t k0, k1;
+            edge_keys(u, v, N, B, k0, k1);
             if (u < 0 || u >= N || v < 0 || v >= N) bad = 1;
             else if (u == v) ++loop;
-            else {
-                k0 = ((uint64_t)u << B) | (uint64_t)v;
-                k1 = ((uint64_t)v << B) | (uint64_t)u;
+            if (keys) {
+                keys[2 * e] = k0;
+                keys[2 * e + 1] = k1;
             }
-            keys[2 * e] = k0;
-            keys[2 * e + 1] = k1;
             if (hist) {
                 atomicAdd(&cnt[w][(unsigned)(k0 >> hist_shift) & 255u], 1);
                 atomicAdd(&cnt[w][(unsigned)(k1 >> hist_shift) & 255u], 1);
@@ -564,9 +563,9 @@ ifgp_status pinned_counters(int64_t **out) {
     return IFGP_OK;
 }
 
-// Keys of E pairs -> 2E keys at keys[0, 2E); self-loop pairs and bad ids
-// counted on the device; with hist, the first radix pass's tile counts of the
-// digit at hist_shift (see ingest_kernel).
+// Keys of E pairs -> 2E keys at keys[0, 2E) (none written if keys is null);
+// self-loop pairs and bad ids counted on the device; with hist, the first
+// radix pass's tile counts of the digit at hist_shift (see ingest_kernel).
 ifgp_status ingest_to(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
                       hipStream_t s, uint64_t *keys, int64_t *ctr, int64_t *hist = nullptr,
                       int hist_shift = 0) {
@@ -642,19 +641,14 @@ int bucket_bits(int64_t N, int64_t nkeys, int B) {
 
 namespace {
 
-// The bucketed build from n unsorted keys (row << B | column, sentinel row N
-// allowed) in `keys`, sorted device-wide by the rows' high bits (rows per
-// bucket 2^sb) with the first pass's tile counts in hist if given; ctr holds
-// what the keys' making counted (self loops, bad ids).  Buckets sorted,
+// The bucketed build from n keys (row << B | column, sentinel row N allowed)
+// sorted by the rows' high bits (rows per bucket 2^sb) into one of the two
+// n-key buffers keys and tmp (`sorted`; the other is scratch); ctr holds what
+// the keys' making counted (self loops, bad ids).  Buckets sorted,
 // deduplicated and counted in LDS; rowptr, counters, plan, relabelled CSR.
-ifgp_status bucket_build(Buf &keys, int64_t n, int64_t N, int B, int sb, int64_t *hist,
-                         Buf &ctr, hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
+ifgp_status bucket_build(Buf &keys, Buf &tmp, uint64_t *sorted, int64_t n, int64_t N, int B,
+                         int sb, Buf &ctr, hipStream_t s, hipStream_t aux, hipEvent_t ev_fork,
                          hipEvent_t ev_join, GraphData &g) {
-    Buf tmp;
-    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
-    uint64_t *sorted = nullptr;
-    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted,
-                            hist));
     uint64_t *other = sorted == keys.as<uint64_t>() ? tmp.as<uint64_t>() : keys.as<uint64_t>();
     const int64_t nbk = (N >> sb) + 1;
     g.N = N;
@@ -744,17 +738,25 @@ ifgp_status build_graph_device(const int64_t *src, const int64_t *dst, int64_t E
     IFGP_TRY(fill_i64(ctr.as<int64_t>(), C_COUNT, 0, s));
     const int64_t n = 2 * E;
     const int sb = bucket_bits(N, n, B);
-    // the first radix pass's histogram is taken while the keys are made
-    Buf hist;
-    const bool passes = B + sb < 2 * B && n > 1;
-    if (passes) IFGP_TRY(alloc(hist, sizeof(int64_t) * 256 * ceil_div(n, (int64_t)RADIX_TILE), s));
-    Buf keys;
+    Buf keys, tmp;
     IFGP_TRY(alloc(keys, sizeof(uint64_t) * n, s));
-    IFGP_TRY(ingest_to(src, dst, E, N, B, s, keys.as<uint64_t>(), ctr.as<int64_t>(),
-                       passes ? hist.as<int64_t>() : nullptr, B + sb));
+    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
+    uint64_t *sorted = keys.as<uint64_t>();
+    if (B + sb < 2 * B && n > 1) {
+        // the first radix pass's histogram taken from the edge lists (ids
+        // checked, loops counted), and the pass itself making the keys from
+        // them: no key array is written and read back in between
+        Buf hist;
+        IFGP_TRY(alloc(hist, sizeof(int64_t) * 256 * ceil_div(n, (int64_t)RADIX_TILE), s));
+        IFGP_TRY(ingest_to(src, dst, E, N, B, s, nullptr, ctr.as<int64_t>(), hist.as<int64_t>(),
+                           B + sb));
+        IFGP_TRY(radix_sort_pairs(src, dst, E, N, B, keys.as<uint64_t>(), tmp.as<uint64_t>(),
+                                  B + sb, 2 * B, s, &sorted, hist.as<int64_t>()));
+    } else {
+        IFGP_TRY(ingest_to(src, dst, E, N, B, s, keys.as<uint64_t>(), ctr.as<int64_t>()));
+    }
     GraphData g;
-    IFGP_TRY(bucket_build(keys, n, N, B, sb, passes ? hist.as<int64_t>() : nullptr, ctr, s, aux,
-                          ev_fork, ev_join, g));
+    IFGP_TRY(bucket_build(keys, tmp, sorted, n, N, B, sb, ctr, s, aux, ev_fork, ev_join, g));
     g.dups = (E - g.self_loops) - g.nnz / 2;
     out = std::move(g);
     return IFGP_OK;
@@ -798,8 +800,12 @@ ifgp_status merge_graph_device(const GraphData &in, const int64_t *src, const in
         IFGP_LAUNCHED();
     }
     IFGP_TRY(ingest_to(src, dst, E, new_N, B, s, keys.as<uint64_t>() + in.nnz, ctr.as<int64_t>()));
+    Buf tmp;
+    IFGP_TRY(alloc(tmp, sizeof(uint64_t) * n, s));
+    uint64_t *sorted = nullptr;
+    IFGP_TRY(radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), n, B + sb, 2 * B, s, &sorted));
     GraphData g;
-    IFGP_TRY(bucket_build(keys, n, new_N, B, sb, nullptr, ctr, s, nullptr, nullptr, nullptr, g));
+    IFGP_TRY(bucket_build(keys, tmp, sorted, n, new_N, B, sb, ctr, s, nullptr, nullptr, nullptr, g));
     g.self_loops += in.self_loops;
     // pairs of this increment that added no new edge
     g.dups = in.dups + (E - (g.self_loops - in.self_loops)) - (g.nnz - in.nnz) / 2;

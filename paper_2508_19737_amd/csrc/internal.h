@@ -20,6 +20,25 @@ ifgp_status fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 constexpr int RADIX_TILE = 4096;
 ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
                            uint64_t **sorted, int64_t *first_hist = nullptr);
+// The same for the 2E keys of E edge pairs (edge_keys below), made from the
+// pairs by the first pass itself (a and b are both 2E long; first_hist, the
+// first pass's counts, is required): the first pass reads the edge lists
+// instead of keys that were written out before.
+ifgp_status radix_sort_pairs(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
+                             uint64_t *a, uint64_t *b, int lo, int hi, hipStream_t s,
+                             uint64_t **sorted, int64_t *first_hist);
+
+// Keys of edge pair (u, v) with B-bit ids: (u << B | v) and (v << B | u); for
+// a self loop or an id outside [0, N), two sentinels N << B.
+__device__ __forceinline__ void edge_keys(int64_t u, int64_t v, int64_t N, int B, uint64_t &k0,
+                                          uint64_t &k1) {
+    if (u < 0 || u >= N || v < 0 || v >= N || u == v) {
+        k0 = k1 = (uint64_t)N << B;
+    } else {
+        k0 = ((uint64_t)u << B) | (uint64_t)v;
+        k1 = ((uint64_t)v << B) | (uint64_t)u;
+    }
+}
 
 // Row classes of the hop kernel, by degree.  Rows are kept in descending-
 // degree order, so each class is a contiguous range of internal rows.

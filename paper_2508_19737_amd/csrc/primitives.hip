@@ -187,8 +187,17 @@ __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *
 // Stable scatter.  Key order within the block is (wave, round, lane).  The
 // tile is first placed in LDS in digit order, then each digit's run is
 // written to its global range by consecutive threads (coalesced stores).
+// Keys read from `in`, or (PAIRS) made from edge pairs: key i is edge_keys of
+// pair i / 2, the first (i even) or the second.
+struct PairKeys {
+    const int64_t *src, *dst;
+    int64_t N;
+    int B;
+};
+
+template <bool PAIRS>
 __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
-    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n, int shift,
+    const uint64_t *__restrict__ in, PairKeys pk, uint64_t *__restrict__ out, int64_t n, int shift,
     const int64_t *__restrict__ offs, int64_t nb) {
     __shared__ int cnt[RS_WAVES][RS_BINS];
     __shared__ int tstart[RS_BINS];
@@ -204,10 +213,28 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
     const uint64_t lt = __lanemask_lt();
     uint64_t key[RS_ROUNDS];
     int rank[RS_ROUNDS];
+    if constexpr (PAIRS) {
+        // every round's pair loaded before any key is made (the loads in
+        // flight together); lanes 2k and 2k + 1 read the same pair
+        int64_t u[RS_ROUNDS], v[RS_ROUNDS];
 #pragma unroll
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        const int64_t idx = t0 + r * 64 + lane;
-        key[r] = idx < n ? in[idx] : 0;
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            const int64_t idx = t0 + r * 64 + lane;
+            u[r] = idx < n ? pk.src[idx >> 1] : 0;
+            v[r] = idx < n ? pk.dst[idx >> 1] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            uint64_t k0, k1;
+            edge_keys(u[r], v[r], pk.N, pk.B, k0, k1);
+            key[r] = (lane & 1) ? k1 : k0;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            const int64_t idx = t0 + r * 64 + lane;
+            key[r] = idx < n ? in[idx] : 0;
+        }
     }
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -263,31 +290,58 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
 }
 }  // namespace
 
-ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
-                           uint64_t **sorted, int64_t *first_hist) {
-    static_assert(RS_TILE == RADIX_TILE, "tile of the fused first histogram");
-    *sorted = a;
-    if (n <= 1 || hi <= lo) return IFGP_OK;
+namespace {
+// The passes over bits [lo, hi) of keys in src (the first pass's counts
+// already in hist if have_first), ping-ponging with dst.
+ifgp_status radix_passes(uint64_t *src, uint64_t *dst, int64_t n, int lo, int hi, hipStream_t s,
+                         uint64_t **sorted, int64_t *hist, bool have_first) {
     const int64_t nb = ceil_div(n, RS_TILE);
-    Buf own;
-    int64_t *hist = first_hist;
-    if (!hist) {
-        IFGP_TRY(alloc(own, sizeof(int64_t) * RS_BINS * nb, s));
-        hist = own.as<int64_t>();
-    }
-    uint64_t *src = a, *dst = b;
     for (int shift = lo; shift < hi; shift += RS_BITS) {
-        if (!(first_hist && shift == lo)) {
+        if (!(have_first && shift == lo)) {
             radix_hist_kernel<<<nb, RS_THREADS, 0, s>>>(src, n, shift, hist, nb);
             IFGP_LAUNCHED();
         }
         IFGP_TRY(exclusive_scan<int64_t>(hist, hist, RS_BINS * nb, nullptr, s));
-        radix_scatter_kernel<<<nb, RS_THREADS, 0, s>>>(src, dst, n, shift, hist, nb);
+        radix_scatter_kernel<false><<<nb, RS_THREADS, 0, s>>>(src, PairKeys{}, dst, n, shift, hist,
+                                                              nb);
         IFGP_LAUNCHED();
         std::swap(src, dst);
     }
     *sorted = src;
     return IFGP_OK;
+}
+}  // namespace
+
+ifgp_status radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n, int lo, int hi, hipStream_t s,
+                           uint64_t **sorted, int64_t *first_hist) {
+    static_assert(RS_TILE == RADIX_TILE, "tile of the fused first histogram");
+    *sorted = a;
+    if (n <= 1 || hi <= lo) return IFGP_OK;
+    Buf own;
+    int64_t *hist = first_hist;
+    if (!hist) {
+        IFGP_TRY(alloc(own, sizeof(int64_t) * RS_BINS * ceil_div(n, RS_TILE), s));
+        hist = own.as<int64_t>();
+    }
+    return radix_passes(a, b, n, lo, hi, s, sorted, hist, first_hist != nullptr);
+}
+
+ifgp_status radix_sort_pairs(const int64_t *src, const int64_t *dst, int64_t E, int64_t N, int B,
+                             uint64_t *a, uint64_t *b, int lo, int hi, hipStream_t s,
+                             uint64_t **sorted, int64_t *first_hist) {
+    const int64_t n = 2 * E, nb = ceil_div(n, RS_TILE);
+    *sorted = a;
+    if (n < 1 || hi <= lo || !first_hist) {
+        set_error("radix_sort_pairs: needs keys, a bit range and the first pass's counts");
+        return IFGP_E_INVALID;
+    }
+    // the first pass: keys made from the pairs, scattered into a
+    IFGP_TRY(exclusive_scan<int64_t>(first_hist, first_hist, RS_BINS * nb, nullptr, s));
+    radix_scatter_kernel<true><<<nb, RS_THREADS, 0, s>>>(nullptr, PairKeys{src, dst, N, B}, a, n, lo,
+                                                         first_hist, nb);
+    IFGP_LAUNCHED();
+    if (lo + RS_BITS >= hi) return IFGP_OK;
+    return radix_passes(a, b, n, lo + RS_BITS, hi, s, sorted, first_hist, false);
 }
 
 }  // namespace ifgp
