@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "wave_match.h"
 
 namespace ifgp {
 namespace {
@@ -154,26 +155,17 @@ struct BucketLds {
     int64_t red[3][waves];
 };
 
-// Valid lanes of the wave whose 8-bit digit equals this lane's.
-__device__ __forceinline__ uint64_t match8(unsigned g, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const bool bit = (g >> b) & 1u;
-        const uint64_t bm = __ballot(bit);
-        m &= bit ? bm : ~bm;
-    }
-    return m;
-}
-
 // Stable in-place sort of sh.a[0, rounds * threads) by the digit
-// (a >> shift) & 255 (callers pad with BK_NONE, which sorts last).  Wave w
-// ranks the keys at [w*rounds*64, (w+1)*rounds*64), so key order is (wave,
-// round, lane).  On return sh.dstart[g] is where digit g starts
-// (sh.dstart[256] = rounds * threads).  Begins and ends with a block
-// barrier; all lanes active.
+// (a >> shift) & 255 (callers pad with BK_NONE, which sorts last).  Keys
+// other than BK_NONE are below 2^top, so where top - shift < 8 the digits
+// are told apart by their low top - shift + 1 bits (BK_NONE's bit
+// top - shift is set, every other key's clear).  Wave w ranks the keys at
+// [w*rounds*64, (w+1)*rounds*64), so key order is (wave, round, lane).  On
+// return sh.dstart[g] is where digit g starts (sh.dstart[256] = rounds *
+// threads).  Begins and ends with a block barrier; all lanes active.
 template <typename Lds>
-__device__ __forceinline__ void lds_digit_pass(Lds &sh, int rounds, int shift) {
+__device__ __forceinline__ void lds_digit_pass(Lds &sh, int rounds, int shift, int top) {
+    const int bits = top - shift < 8 ? top - shift + 1 : 8;
     constexpr int KPL = Lds::kpl;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int base = w * rounds * 64 + lane;
@@ -190,7 +182,7 @@ __device__ __forceinline__ void lds_digit_pass(Lds &sh, int rounds, int shift) {
         if (r % 2 == 0) rank2[r / 2] = 0;
         if (r < rounds) {  // uniform over the block
             const unsigned g = (key[r] >> shift) & (BK_BINS - 1);
-            const uint64_t m = match8(g, true);
+            const uint64_t m = match_digit8(g, true, bits);
             const int below = __popcll(m & lt);
             const int c = sh.cnt[w][g];
             // the leader's write follows every lane's read of this wave
@@ -412,7 +404,7 @@ __global__ __launch_bounds__(BK_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
         }
     }
     if (rounds > 0)
-        for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
+        for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift, s + B);
     bucket_survivors(sh, sh.a, n, B, tcol + bs);
     bucket_degrees(sh, b, s, N, deg, stats);
 }
@@ -443,7 +435,7 @@ __global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
             const int rounds = (int)((n + T - 1) / T);
             for (int i = tid; i < rounds * T; i += T)
                 sh.a[i] = i < n ? local_key(keys[bs + i], N, B, s) : BK_NONE;
-            for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift);
+            for (int shift = 0; shift < s + B; shift += 8) lds_digit_pass(sh, rounds, shift, s + B);
             bucket_survivors(sh, sh.a, n, B, tcol + bs);
             bucket_degrees(sh, b, s, N, deg, stats);
             __syncthreads();
@@ -464,7 +456,7 @@ __global__ __launch_bounds__(BK_BIG_THREADS) void bucket_big_kernel(
                 // padding (BK_NONE, digit 255) sorts after every key of the chunk
                 for (int i = tid; i < rounds * T; i += T)
                     sh.a[i] = i < m ? x[c0 + i] : BK_NONE;
-                lds_digit_pass(sh, rounds, shift);
+                lds_digit_pass(sh, rounds, shift, s + B);
                 for (int i = tid; i < m; i += T) {
                     const uint32_t k = sh.a[i];
                     const unsigned g = (k >> shift) & (BK_BINS - 1);

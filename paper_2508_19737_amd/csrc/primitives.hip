@@ -6,6 +6,7 @@
 // are found by matching the digit bit by bit), so no LDS atomics contend when
 // many keys share a digit.
 #include "internal.h"
+#include "wave_match.h"
 
 namespace ifgp {
 
@@ -138,20 +139,8 @@ constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_ROUNDS = 16;                       // keys per lane
 constexpr int RS_WAVE_TILE = 64 * RS_ROUNDS;        // 1024 keys per wave
 constexpr int RS_TILE = RS_WAVES * RS_WAVE_TILE;    // 4096 keys per block
-constexpr int RS_BITS = 8;
+constexpr int RS_BITS = 8;  // the digit of match_digit8
 constexpr int RS_BINS = 1 << RS_BITS;
-
-// Mask of the valid lanes of this wave whose digit equals this lane's digit.
-__device__ __forceinline__ uint64_t match_digit(unsigned g, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < RS_BITS; ++b) {
-        const bool bit = (g >> b) & 1u;
-        const uint64_t bm = __ballot(bit);
-        m &= bit ? bm : ~bm;
-    }
-    return m;
-}
 
 // Per-block digit counts, digit-major: hist[digit * nb + block].
 __global__ __launch_bounds__(RS_THREADS) void radix_hist_kernel(const uint64_t *__restrict__ keys,
@@ -240,7 +229,7 @@ __global__ __launch_bounds__(RS_THREADS) void radix_scatter_kernel(
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const bool valid = t0 + r * 64 + lane < n;
         const unsigned g = (unsigned)(key[r] >> shift) & (RS_BINS - 1);
-        const uint64_t m = match_digit(g, valid);
+        const uint64_t m = match_digit8(g, valid);
         const int below = __popcll(m & lt);
         int c = 0;
         if (valid) c = cnt[w][g];
