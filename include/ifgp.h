@@ -388,10 +388,14 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
  * centroids and what is known of each row stay in device memory held by the
  * tree (about 24 bytes per row, 12 Dp per cluster, Dp = d rounded up to 8,
  * 16, 32 or 64, up to 16 bytes per row and entry chunk for a pass's partial
- * results, and 68 bytes per row left to the FP64 rule).  The call synchronises hip_stream (after the upload of
- * the changed centroids, and before each pass, whose size it reads back).
+ * results, and 68 bytes per row left to the FP64 rule).  The call
+ * synchronises hip_stream (after the upload of the changed centroids, and
+ * before each pass, whose size it reads back).
  * Z: device, n x d FP32, d <= 64; labels: device int32 n.  Errors as
- * ifgp_birch_predict.
+ * ifgp_birch_predict, plus IFGP_E_INVALID for n >= 2^31.  A call that fails
+ * part-way (IFGP_E_OOM, IFGP_E_HIP) leaves labels undefined and drops what
+ * the tree kept for updates: the next call uploads every centroid again and
+ * labels all of its rows in full.
  */
 IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, int64_t n,
                                                int32_t *labels, void *hip_stream);

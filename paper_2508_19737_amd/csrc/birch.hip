@@ -1757,6 +1757,48 @@ ifgp_status partial_fit(ifgp_birch_t b, const float *Z, int64_t n, int Z_on_devi
 }
 }  // namespace ifgp
 
+namespace ifgp {
+// The update itself (ifgp_birch_predict_update checks the arguments and, on
+// any failure here, drops the label state).  Rows [0, L.n_prev) were labelled
+// by the previous update.
+ifgp_status predict_update(ifgp_birch_s *b, const float *Z, int64_t n, int32_t *labels,
+                           hipStream_t s) {
+    LabelState &L = b->ls;
+    const int64_t n_old = L.n_prev;
+    Upload up;
+    IFGP_TRY(upload_changes(b, s, &up));
+    if (n > L.cap_pts) {
+        const int64_t cap = std::max<int64_t>(n, L.cap_pts * 3 / 2);
+        Buf bid, b32, s32, lists;
+        IFGP_TRY(alloc(bid, sizeof(int32_t) * cap, s));
+        IFGP_TRY(alloc(b32, sizeof(float) * cap, s));
+        IFGP_TRY(alloc(s32, sizeof(float) * cap, s));
+        IFGP_TRY(alloc(lists, sizeof(int32_t) * 3 * cap, s));
+        if (n_old > 0) {
+            IFGP_HIP(hipMemcpyAsync(bid.p, L.best_id.p, sizeof(int32_t) * n_old, hipMemcpyDeviceToDevice, s));
+            IFGP_HIP(hipMemcpyAsync(b32.p, L.best32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
+            IFGP_HIP(hipMemcpyAsync(s32.p, L.second32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
+        }
+        L.best_id = std::move(bid);
+        L.best32 = std::move(b32);
+        L.second32 = std::move(s32);
+        L.lists = std::move(lists);
+        L.cap_pts = cap;
+    }
+    IFGP_TRY(ensure(L.counters, sizeof(int32_t) * 2, s));
+    if (!L.hcount) IFGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&L.hcount), 64, 0));
+    switch (b->Dp) {
+    case 8: return label_passes<8>(b, Z, n, n_old, up, labels, s);
+    case 16: return label_passes<16>(b, Z, n, n_old, up, labels, s);
+    case 32: return label_passes<32>(b, Z, n, n_old, up, labels, s);
+    case 64: return label_passes<64>(b, Z, n, n_old, up, labels, s);
+    default:
+        set_error("ifgp_birch_predict_update: device labelling supports d <= 64");
+        return IFGP_E_INVALID;
+    }
+}
+}  // namespace ifgp
+
 extern "C" {
 
 IFGP_API ifgp_status ifgp_birch_info(ifgp_birch_t b, int64_t *n_points, int64_t *n_clusters,
@@ -1864,48 +1906,22 @@ IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, i
         b->device = dev;
         b->dirty = true;
     }
-    const hipStream_t s = (hipStream_t)hip_stream;
     LabelState &L = b->ls;
     b->Dp = padded_dim(b->d);
-    const int d = b->d, Dp = b->Dp;
     if (n < L.n_prev) L.n_prev = 0;  // not the rows labelled before: start over
-    const int64_t n_old = L.n_prev;
-    Upload up;
+    ifgp_status st = IFGP_OK;
     try {
-        IFGP_TRY(upload_changes(b, s, &up));
+        st = predict_update(b, Z, n, labels, (hipStream_t)hip_stream);
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
-        return IFGP_E_OOM;
-    }
-    if (n > L.cap_pts) {
-        const int64_t cap = std::max<int64_t>(n, L.cap_pts * 3 / 2);
-        Buf bid, b32, s32;
-        IFGP_TRY(alloc(bid, sizeof(int32_t) * cap, s));
-        IFGP_TRY(alloc(b32, sizeof(float) * cap, s));
-        IFGP_TRY(alloc(s32, sizeof(float) * cap, s));
-        if (n_old > 0) {
-            IFGP_HIP(hipMemcpyAsync(bid.p, L.best_id.p, sizeof(int32_t) * n_old, hipMemcpyDeviceToDevice, s));
-            IFGP_HIP(hipMemcpyAsync(b32.p, L.best32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
-            IFGP_HIP(hipMemcpyAsync(s32.p, L.second32.p, sizeof(float) * n_old, hipMemcpyDeviceToDevice, s));
-        }
-        IFGP_TRY(alloc(L.lists, sizeof(int32_t) * 3 * cap, s));
-        L.best_id = std::move(bid);
-        L.best32 = std::move(b32);
-        L.second32 = std::move(s32);
-        L.cap_pts = cap;
-    }
-    IFGP_TRY(ensure(L.counters, sizeof(int32_t) * 2, s));
-    if (!L.hcount) IFGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&L.hcount), 64, 0));
-    ifgp_status st = IFGP_OK;
-    switch (Dp) {
-    case 8: st = label_passes<8>(b, Z, n, n_old, up, labels, s); break;
-    case 16: st = label_passes<16>(b, Z, n, n_old, up, labels, s); break;
-    case 32: st = label_passes<32>(b, Z, n, n_old, up, labels, s); break;
-    case 64: st = label_passes<64>(b, Z, n, n_old, up, labels, s); break;
-    default: break;
+        st = IFGP_E_OOM;
     }
     if (st != IFGP_OK) {
-        L.n_prev = 0;  // the points' state is not known: the next update starts over
+        // the upload may have taken the tree's changes without the device or
+        // the points' state following them, and a failed allocation leaves
+        // its buffer empty: the label state is dropped, and the next update
+        // allocates it again, uploads every entry and labels every point
+        L.reset();
         return st;
     }
     L.n_prev = n;

@@ -119,3 +119,37 @@ def test_device_entry_point_argument_errors(ifgp):
     G.destroy()
     with pytest.raises(ifgp.IfgpError):
         G.info()
+
+
+def test_label_update_after_allocation_failures(ifgp):
+    """An update that fails part-way (here: a device allocation refused at
+    different points of it) must not leave labels or entries stale: the next
+    update gives the full FP64 labelling's labels exactly."""
+    import torch
+    rng = np.random.default_rng(7)
+    d, total = 16, 12000
+    X = torch.as_tensor((0.3 * rng.standard_normal((total, d))).astype(np.float32), device="cuda")
+    b = ifgp.Birch(d, 0.5, 50)
+    labels = torch.empty(total, dtype=torch.int32, device="cuda")
+    n = 3000
+    b.partial_fit(X[:n])
+    b.predict_update(X[:n], out=labels[:n])
+    failures = 0
+    with Budget(ifgp) as bud:
+        for budget in [0, 256, 4096, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 0, 1 << 12]:
+            m = n + 1000
+            b.partial_fit(X[n:m])
+            n = m
+            bud.left = budget
+            try:
+                b.predict_update(X[:n], out=labels[:n])
+            except ifgp.IfgpError as e:
+                assert e.status == -3
+                failures += 1
+            bud.left = 1 << 62
+            b.predict_update(X[:n], out=labels[:n])
+            full = b.predict(X[:n])
+            torch.cuda.synchronize()
+            assert torch.equal(full, labels[:n]), f"budget {budget}: labels differ after a failed update"
+    assert failures >= 3
+    b.destroy()
