@@ -32,7 +32,9 @@
  *     build, stream_add, export) synchronise it themselves.
  *   - A graph handle owns all device memory it allocated (through the
  *     allocator hook, see ifgp_set_allocator; by default the library's
- *     caching allocator) and releases it stream-ordered on the stream each
+ *     caching allocator) and releases it stream-ordered: a block that a call
+ *     replaces on the stream of that call (calls on one handle must be
+ *     ordered, so its earlier uses come first), the rest on the stream each
  *     block was allocated on.  Work that uses a handle on other
  *     streams must be complete before ifgp_stream_add or ifgp_destroy on it.
  *     A handle is not thread-safe; distinct handles may be used from
@@ -259,8 +261,10 @@ IFGP_API ifgp_status ifgp_footprint_bytes(int64_t N, int64_t nnz, int32_t d, int
  * by later allocations on the same stream.  Each block is released through
  * the allocator that produced it, so the hook may change at any time.  alloc(bytes, stream,
  * ctx) returns device memory usable on `stream` or NULL; free(ptr, stream,
- * ctx) releases it.  Process-wide; keep the callbacks alive while any block
- * they produced exists.
+ * ctx) releases it after the work already enqueued on `stream`, which may
+ * differ from the stream it was allocated on (a hook that cannot order the
+ * release on `stream` synchronises it first).  Process-wide; keep the
+ * callbacks alive while any block they produced exists.
  */
 IFGP_API ifgp_status ifgp_set_allocator(void *(*alloc)(size_t, void *, void *),
                                void (*free_fn)(void *, void *, void *), void *ctx);

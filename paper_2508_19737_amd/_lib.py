@@ -156,13 +156,22 @@ def use_torch_allocator():
     raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc
     raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
 
+    owner = {}   # block -> the stream it was allocated on
+
     def _alloc(size, stream, ctx):
         try:
-            return raw_alloc(int(size), int(stream or 0))
+            p = raw_alloc(int(size), int(stream or 0))
         except Exception:   # out of memory: the library reports IFGP_E_OOM
             return None
+        owner[p] = int(stream or 0)
+        return p
 
     def _free(ptr, stream, ctx):
+        # torch hands a released block out again at once to allocations on
+        # the stream it was allocated on; released on another stream (the
+        # one that used it last), that stream's work must finish first
+        if owner.pop(int(ptr), None) != int(stream or 0):
+            torch.cuda.synchronize()
         raw_delete(int(ptr))
 
     hooks = (_ALLOC_T(_alloc), _FREE_T(_free))

@@ -39,6 +39,8 @@ namespace {
 // kept per (device, stream) and handed out again only to allocations on the
 // same stream, which are ordered after every earlier use of the block on that
 // stream (the release is stream-ordered, as with torch's caching allocator).
+// A block's device is the one it was allocated on, whichever is current when
+// it is released.
 // A request reuses the smallest cached block of at least its size and at most
 // twice its size; when hipMalloc fails, the whole cache is released and the
 // allocation retried.
@@ -67,14 +69,14 @@ class BlockCache {
             }
         }
         std::lock_guard<std::mutex> lk(mu_);
-        size_[p] = bytes;
+        size_[p] = {bytes, dev};
         return p;
     }
     void put(void *p, hipStream_t s) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
         std::lock_guard<std::mutex> lk(mu_);
-        free_[{dev, s}].insert({size_[p], p});
+        const auto it = size_.find(p);
+        if (it == size_.end()) return;  // not a block of this cache
+        free_[{it->second.second, s}].insert({it->second.first, p});
     }
     // hipFree every cached block (implicitly synchronises the device).
     void release_all() {
@@ -90,7 +92,7 @@ class BlockCache {
   private:
     std::mutex mu_;
     std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_;
-    std::unordered_map<void *, size_t> size_;
+    std::unordered_map<void *, std::pair<size_t, int>> size_;  // bytes, device
 };
 
 BlockCache &cache() {
@@ -132,6 +134,10 @@ void raw_free(void *p, hipStream_t s, FreeFn free_fn, void *ctx) {
 }
 
 ifgp_status alloc(Buf &b, size_t bytes, hipStream_t s) {
+    // a block being replaced is released on the stream of the call replacing
+    // it: calls on a handle are ordered, so every earlier use of the block
+    // comes before that stream's later work
+    if (b.p) b.s = s;
     b.reset();
     const size_t n = bytes < 256 ? 256 : ((bytes + 255) / 256) * 256;
     FreeFn fn = nullptr;

@@ -329,10 +329,15 @@ struct LabelState {
         if (stage) (void)hipHostFree(stage);
         if (hcount) (void)hipHostFree(hcount);
     }
-    void reset() {
-        f32.reset(); f64.reset(); cn32.reset(); cn64.reset(); gidx.reset(); chg.reset();
-        cmp.reset(); raw.reset(); best_id.reset(); best32.reset(); second32.reset(); lists.reset();
-        counters.reset(); part.reset(); ncand.reset(); cand.reset();
+    // Drop every device buffer (each released on stream s if given, else on
+    // the stream it was allocated on) and what is known of entries and rows.
+    void reset(hipStream_t s = nullptr, bool on_s = false) {
+        Buf *all[] = {&f32, &f64, &cn32, &cn64, &gidx, &chg, &cmp, &raw, &best_id, &best32,
+                      &second32, &lists, &counters, &part, &ncand, &cand};
+        for (Buf *x : all) {
+            if (on_s) x->s = s;
+            x->reset();
+        }
         cap_blk = cmp_blk = cap_pts = n_prev = 0;
         slots_valid = false;
         twins.clear();
@@ -1758,6 +1763,21 @@ ifgp_status partial_fit(ifgp_birch_t b, const float *Z, int64_t n, int Z_on_devi
 }  // namespace ifgp
 
 namespace ifgp {
+// The device copies (centroids, label state) belong to the device they were
+// made on: when the current device is another, they are dropped (each block
+// goes back to its own device's cache) and made again on this one.
+ifgp_status use_current_device(ifgp_birch_s *b) {
+    int dev = 0;
+    IFGP_HIP(hipGetDevice(&dev));
+    if (b->device != dev) {
+        b->centers.reset();
+        b->ls.reset();
+        b->device = dev;
+        b->dirty = true;
+    }
+    return IFGP_OK;
+}
+
 // The update itself (ifgp_birch_predict_update checks the arguments and, on
 // any failure here, drops the label state).  Rows [0, L.n_prev) were labelled
 // by the previous update.
@@ -1842,13 +1862,7 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
         return IFGP_E_STATE;
     }
     if (n == 0) return IFGP_OK;
-    int dev = 0;
-    IFGP_HIP(hipGetDevice(&dev));
-    if (b->device != dev) {  // the device copy belongs to one device
-        b->centers.reset();
-        b->device = dev;
-        b->dirty = true;
-    }
+    IFGP_TRY(use_current_device(b));
     const hipStream_t s = (hipStream_t)hip_stream;
     try {
         IFGP_TRY(upload_centers(b, s));
@@ -1898,14 +1912,7 @@ IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, i
         return IFGP_E_INVALID;
     }
     if (n == 0) return IFGP_OK;
-    int dev = 0;
-    IFGP_HIP(hipGetDevice(&dev));
-    if (b->device != dev) {  // the device copies belong to one device
-        b->centers.reset();
-        b->ls.reset();
-        b->device = dev;
-        b->dirty = true;
-    }
+    IFGP_TRY(use_current_device(b));
     LabelState &L = b->ls;
     b->Dp = padded_dim(b->d);
     if (n < L.n_prev) L.n_prev = 0;  // not the rows labelled before: start over
@@ -1919,9 +1926,10 @@ IFGP_API ifgp_status ifgp_birch_predict_update(ifgp_birch_t b, const float *Z, i
     if (st != IFGP_OK) {
         // the upload may have taken the tree's changes without the device or
         // the points' state following them, and a failed allocation leaves
-        // its buffer empty: the label state is dropped, and the next update
-        // allocates it again, uploads every entry and labels every point
-        L.reset();
+        // its buffer empty: the label state is dropped (released after this
+        // call's work on its stream), and the next update allocates it
+        // again, uploads every entry and labels every point
+        L.reset((hipStream_t)hip_stream, true);
         return st;
     }
     L.n_prev = n;

@@ -153,3 +153,35 @@ def test_label_update_after_allocation_failures(ifgp):
             assert torch.equal(full, labels[:n]), f"budget {budget}: labels differ after a failed update"
     assert failures >= 3
     b.destroy()
+
+
+def test_handle_on_two_streams(ifgp):
+    """One handle used on two streams in order (the second waits for the
+    first), under both allocators: the blocks the second stream's calls
+    replace (a wider embedding's workspace, the build's survivors when the
+    canonical column indices are made) are released after that stream's
+    work, and every result equals the one-stream result."""
+    import torch
+    g = dcsbm(6000, 12, seed=4)
+    R = ifgp.Graph(g.src, g.dst, g.N)
+    ref16 = R.embed(-1.0, 6, 16, 2).cpu()
+    ref64 = R.embed(-1.0, 6, 64, 2).cpu()
+    ref_csr = R.export_csr()
+    R.destroy()
+    for hook in (True, False):
+        if hook:
+            ifgp.use_torch_allocator()
+        A, B = torch.cuda.Stream(), torch.cuda.Stream()
+        with torch.cuda.stream(A):
+            G = ifgp.Graph(g.src, g.dst, g.N, stream=A)
+            z16 = G.embed(-1.0, 6, 16, 2, stream=A)
+        B.wait_stream(A)
+        with torch.cuda.stream(B):
+            z64 = G.embed(-1.0, 6, 64, 2, stream=B)
+            csr = G.export_csr()
+        B.synchronize()
+        assert torch.equal(z16.cpu(), ref16) and torch.equal(z64.cpu(), ref64)
+        assert all(np.array_equal(x, y) for x, y in zip(csr, ref_csr))
+        G.destroy()
+        ifgp.use_hip_allocator()
+    ifgp.empty_cache()
