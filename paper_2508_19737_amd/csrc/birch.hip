@@ -88,6 +88,7 @@ uint64_t twin_key(const double *c, int d, double cn) {
 // share the vector lanes.
 __attribute__((always_inline)) inline void dots_block(const double *blk, const double *p, int d,
                                                       double *out) {
+#pragma clang fp contract(off)
     v4_t s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int j = 0; j < d; ++j) {
         const double *r = blk + (size_t)j * NB;
@@ -108,14 +109,52 @@ __attribute__((always_inline)) inline void dots_block(const double *blk, const d
     std::memcpy(out + 12, &s3, sizeof(v4_t));
 }
 
+// The same for two consecutive blocks (2 NB entries): eight independent sums
+// per coordinate instead of four, so that the additions' latency, not their
+// count, no longer sets the pace; each entry's sum is still taken over the
+// coordinates in order.
+__attribute__((always_inline)) inline void dots_block2(const double *blk, const double *p, int d,
+                                                       double *out) {
+#pragma clang fp contract(off)
+    v4_t s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = 0.0;
+    const double *blk1 = blk + (size_t)NB * d;
+    for (int j = 0; j < d; ++j) {
+        const double *r0 = blk + (size_t)j * NB, *r1 = blk1 + (size_t)j * NB;
+        const v4_t pj = p[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v4_t c0, c1;
+            std::memcpy(&c0, r0 + 4 * q, sizeof(v4_t));
+            std::memcpy(&c1, r1 + 4 * q, sizeof(v4_t));
+            s[q] = s[q] + c0 * pj;
+            s[4 + q] = s[4 + q] + c1 * pj;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        std::memcpy(out + 4 * q, &s[q], sizeof(v4_t));
+        std::memcpy(out + NB + 4 * q, &s[4 + q], sizeof(v4_t));
+    }
+}
+
+// c_k . p for the entries [k0, k0 + 2 NB) (the second block only if k0 + NB
+// < m: blocks are allocated whole, so a block with an entry is readable).
+__attribute__((always_inline)) inline void dots_pair(const double *ct, int m, int k0,
+                                                     const double *p, int d, double *out) {
+    if (k0 + NB < m) dots_block2(ct + (size_t)k0 * d, p, d, out);
+    else dots_block(ct + (size_t)k0 * d, p, d, out);
+}
+
 __attribute__((always_inline)) inline int nearest_body(const double *ct, const double *cn, int m,
                                                        const double *p, int d) {
-    double dots[NB];
+    double dots[2 * NB];
     int best = 0;
     double bd = 0.0;
-    for (int k0 = 0; k0 < m; k0 += NB) {
-        dots_block(ct + (size_t)k0 * d, p, d, dots);
-        const int e = m - k0 < NB ? m - k0 : NB;
+    for (int k0 = 0; k0 < m; k0 += 2 * NB) {
+        dots_pair(ct, m, k0, p, d, dots);
+        const int e = m - k0 < 2 * NB ? m - k0 : 2 * NB;
         for (int l = 0; l < e; ++l) {
             const double dk = cn[k0 + l] - 2.0 * dots[l];
             if (k0 + l == 0 || dk < bd) {
@@ -127,10 +166,15 @@ __attribute__((always_inline)) inline int nearest_body(const double *ct, const d
     return best;
 }
 
-// c_k . p for every entry k < m (out has room for m rounded up to NB).
+// c_k . p for every entry k < m (out has room for m rounded up to 2 NB).
 __attribute__((always_inline)) inline void dots_body(const double *ct, int m, const double *p,
                                                      int d, double *out) {
-    for (int k0 = 0; k0 < m; k0 += NB) dots_block(ct + (size_t)k0 * d, p, d, out + k0);
+    double two[2 * NB];
+    for (int k0 = 0; k0 < m; k0 += 2 * NB) {
+        dots_pair(ct, m, k0, p, d, two);
+        const int e = m - k0 < 2 * NB ? m - k0 : 2 * NB;
+        std::memcpy(out + k0, two, sizeof(double) * e);
+    }
 }
 
 __attribute__((target("avx2"))) int nearest_avx2(const double *ct, const double *cn, int m,
@@ -154,6 +198,7 @@ bool use_avx2() {
     static const bool yes = __builtin_cpu_supports("avx2");  // known by the first call
     return yes;
 }
+
 
 
 }  // namespace
@@ -390,16 +435,23 @@ BNode *new_node(ifgp_birch_s *t, bool leaf) {
     return x;
 }
 
+// Entry k's centroid x->c[k] is in place and cn is its squared norm: the
+// coordinate-major copy, the norm and (in a leaf) the twin key follow.
+void store_centroid(BNode *x, int k, int d, double cn) {
+    const double *c = &x->c[(size_t)k * d];
+    double *blk = &x->ct[(size_t)(k / NB) * NB * d + k % NB];
+    for (int j = 0; j < d; ++j) blk[(size_t)j * NB] = c[j];
+    x->cn[k] = cn;
+    if (x->leaf) x->key[k] = twin_key(c, d, cn);
+}
+
 // Entry k's centroid and its squared norm from its CF.
 void refresh(BNode *x, int k, int d) {
     double *c = &x->c[(size_t)k * d];
     const double *ls = &x->ls[(size_t)k * d];
     const double nk = (double)x->n[k];
     for (int j = 0; j < d; ++j) c[j] = ls[j] / nk;
-    double *blk = &x->ct[(size_t)(k / NB) * NB * d + k % NB];
-    for (int j = 0; j < d; ++j) blk[(size_t)j * NB] = c[j];
-    x->cn[k] = dot(c, c, d);
-    if (x->leaf) x->key[k] = twin_key(c, d, x->cn[k]);
+    store_centroid(x, k, d, dot(c, c, d));
 }
 
 void append(BNode *x, int d, int64_t n, const double *ls, double ss, BNode *child,
@@ -413,6 +465,24 @@ void append(BNode *x, int d, int64_t n, const double *ls, double ss, BNode *chil
     x->cn.push_back(0.0);
     x->child.push_back(child);
     refresh(x, x->size() - 1, d);
+}
+
+// Entry i of x appended to y as it is: its CF, identity and child, and the
+// centroid, norm and twin key refresh made from that CF (a split moves
+// entries without changing them).
+void move_entry(BNode *y, const BNode *x, int i, int d) {
+    const double *ls = &x->ls[(size_t)i * d], *c = &x->c[(size_t)i * d];
+    y->id.push_back(x->id[i]);
+    y->key.push_back(x->key[i]);
+    y->n.push_back(x->n[i]);
+    y->ls.insert(y->ls.end(), ls, ls + d);
+    y->ss.push_back(x->ss[i]);
+    y->c.insert(y->c.end(), c, c + d);
+    y->cn.push_back(x->cn[i]);
+    y->child.push_back(x->child[i]);
+    const int k = y->size() - 1;
+    double *blk = &y->ct[(size_t)(k / NB) * NB * d + k % NB];
+    for (int j = 0; j < d; ++j) blk[(size_t)j * NB] = c[j];
 }
 
 // CF of a whole node (its entries summed in order).
@@ -471,7 +541,7 @@ std::pair<BNode *, BNode *> split(ifgp_birch_s *t, BNode *x) {
     BNode *a = new_node(t, x->leaf), *b = new_node(t, x->leaf);
     for (int i = 0; i < k; ++i) {
         const bool to_a = i == p || dist(p, i) < dist(q, i);
-        append(to_a ? a : b, d, x->n[i], &x->ls[(size_t)i * d], x->ss[i], x->child[i], x->id[i]);
+        move_entry(to_a ? a : b, x, i, d);
     }
     if (x->leaf) {
         a->prev_leaf = x->prev_leaf;
@@ -538,11 +608,15 @@ bool insert(ifgp_birch_s *t, BNode *x, const double *p, double pp, std::vector<d
     for (int j = 0; j < d; ++j) ls1[j] = x->ls[(size_t)k * d + j] + p[j];
     const double ss1 = x->ss[k] + pp;
     for (int j = 0; j < d; ++j) c1[j] = ls1[j] / (double)n1;
-    if (ss1 / (double)n1 - dot(c1, c1, d) <= t->T * t->T) {
+    const double cn1 = dot(c1, c1, d);
+    if (ss1 / (double)n1 - cn1 <= t->T * t->T) {
+        // the absorbed CF's centroid and norm are c1 and cn1, the values
+        // refresh would compute again from it
         x->n[k] = n1;
         std::memcpy(&x->ls[(size_t)k * d], ls1, sizeof(double) * d);
         x->ss[k] = ss1;
-        refresh(x, k, d);
+        std::memcpy(&x->c[(size_t)k * d], c1, sizeof(double) * d);
+        store_centroid(x, k, d, cn1);
         mark_changed(t, x->id[k]);
         return false;
     }
