@@ -97,3 +97,53 @@ def test_random_configuration(ifgp, i):
     log(f"sweep case {i}: rel_frobenius={err:.3e}")
     assert np.all(np.isfinite(got))
     assert err <= TOL[storage], (i, err)
+
+
+STREAMS = 12
+
+
+@pytest.mark.parametrize("i", range(STREAMS))
+def test_random_stream(ifgp, i):
+    """A seeded random stream: a graph of 1 to 5,000 nodes and five increments
+    that add nodes (N growing across powers of two, so the key width
+    changes), or none, with fresh pairs, self loops, repeats within the
+    increment and repeats of edges already resident (some increments empty or
+    holding only repeats).  After each: CSR and counts equal the oracle's for
+    the cumulative edge list, and the embedding equals a fresh build's."""
+    rng = np.random.default_rng(5000 + i)
+    N = int(np.exp(rng.uniform(0.0, np.log(5000.0)))) + 1
+    E0 = int(N * rng.uniform(0.0, 8.0))
+    src, dst = random_edges(N, E0, int(rng.integers(0, 2**31)), self_loops=0.05, dup=0.2)
+    log(f"stream case {i}: N={N} E={E0}")
+    G = ifgp.Graph(src, dst, N)
+    d, K = int(rng.choice([8, 17, 32])), int(rng.integers(1, 5))
+    for t in range(5):
+        grow = rng.random()
+        new_N = N if grow < 0.3 else int(N * rng.uniform(1.0, 3.0)) + 1
+        kind = rng.random()
+        if kind < 0.15:
+            s, dd = np.zeros(0, np.int64), np.zeros(0, np.int64)
+        elif kind < 0.3 and len(src):
+            pick = rng.integers(0, len(src), size=int(rng.integers(1, 200)))
+            s, dd = dst[pick], src[pick]          # only repeats of resident edges
+        else:
+            E = int(new_N * rng.uniform(0.0, 4.0))
+            s, dd = random_edges(new_N, E, int(rng.integers(0, 2**31)), self_loops=0.05, dup=0.2)
+            if len(src):
+                pick = rng.integers(0, len(src), size=min(len(src), 100))
+                s, dd = np.concatenate([s, src[pick]]), np.concatenate([dd, dst[pick]])
+        log(f"stream case {i} step {t}: new_N={new_N} E={len(s)}")
+        G.stream_add(s, dd, new_N=new_N)
+        N = new_N
+        src, dst = np.concatenate([src, s]), np.concatenate([dst, dd])
+        rp, ci, loops, dups = ffp.canonical_csr(src, dst, N)
+        grp, gci, _ = G.export_csr()
+        assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci), (i, t)
+        assert G.info() == {"N": N, "nnz": int(rp[-1]), "self_loops_dropped": loops,
+                            "dups_dropped": dups}, (i, t)
+        got = G.embed(-0.5, K, d, 9).cpu().numpy()
+        F = ifgp.Graph(src, dst, N)
+        fresh = F.embed(-0.5, K, d, 9).cpu().numpy()
+        F.destroy()
+        assert np.array_equal(got, fresh), (i, t)
+    G.destroy()
