@@ -348,3 +348,33 @@ def test_label_update_ties_within_one_lane(ifgp):
     assert np.array_equal(upd, full), np.flatnonzero(upd != full)[:10]
     check_labels(X, C, upd)
     b.destroy()
+
+
+@pytest.mark.parametrize("i", range(12))
+def test_label_update_random_sweep(ifgp, i):
+    """Seeded random configurations of the update path: width (1 to 64),
+    number of rows and of planted clusters, data scale (a power of two),
+    spread, threshold, branching factor and the batch cuts drawn per case; a
+    share of the rows snapped to a grid of 1/8 of the scale (exact repeats,
+    twin entries and exact ties) and a share repeated verbatim.  At every
+    step the update path equals the full FP64 labelling and the oracle's
+    argmin (up to rounding ties)."""
+    rng = np.random.default_rng(7000 + i)
+    d = int(rng.choice([1, 2, 3, 5, 8, 13, 16, 24, 31, 32, 47, 64]))
+    n = int(rng.integers(500, 12_000))
+    k = int(rng.integers(2, 80))
+    scale = float(2.0 ** int(rng.integers(-6, 7)))
+    spread = float(rng.uniform(0.01, 0.3))
+    X = rng.random((k, d))[rng.integers(0, k, size=n)] + rng.normal(size=(n, d)) * spread
+    snap = rng.random(n) < rng.uniform(0.0, 0.5)
+    X[snap] = np.round(X[snap] * 8.0) / 8.0
+    rep = np.flatnonzero(rng.random(n) < 0.2)
+    X[rep] = X[rng.integers(0, n, size=rep.size)]
+    X = (X * scale).astype(np.float32)
+    thr = float(rng.uniform(0.2, 2.0)) * spread * scale * np.sqrt(d)
+    B = int(rng.integers(3, 61))
+    steps = int(rng.integers(2, 7))
+    cuts = [0] + sorted(int(x) for x in rng.choice(np.arange(1, n), size=steps - 1, replace=False)) + [n]
+    log(f"label update sweep {i}: n={n} d={d} k={k} scale={scale} spread={spread:.3f} "
+        f"threshold={thr:.4g} B={B} cuts={cuts}")
+    _steps(ifgp, X, cuts, thr, B)
