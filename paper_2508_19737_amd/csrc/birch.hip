@@ -497,15 +497,6 @@ void summary(const BNode *x, int d, int64_t &n, std::vector<double> &ls, double 
     }
 }
 
-// Ask for the blocks the next nearest() will read, all at once.
-inline void prefetch_node(const BNode *x, int d) {
-    const char *a = (const char *)x->ct.data();
-    const size_t bytes = (size_t)((x->size() + NB - 1) / NB) * NB * d * sizeof(double);
-    for (size_t o = 0; o < bytes; o += 64) __builtin_prefetch(a + o);
-    const char *c = (const char *)x->cn.data();
-    for (size_t o = 0; o < x->cn.size() * sizeof(double); o += 64) __builtin_prefetch(c + o);
-}
-
 // The entry whose centroid is nearest to p (first on ties), by
 // |c_k|^2 - 2 c_k . p.
 int nearest(const BNode *x, const double *p, int d) {
@@ -581,6 +572,13 @@ bool insert(ifgp_birch_s *t, BNode *x, const double *p, double pp, std::vector<d
     const int k = nearest(x, p, d);
     if (!x->leaf) {
         BNode *ch = x->child[k];
+        // entry k takes p before the descent (the update does not depend on
+        // it, and a split below rewrites the entry from its two halves), so
+        // that its refresh overlaps the child's search
+        x->n[k] += 1;
+        for (int j = 0; j < d; ++j) x->ls[(size_t)k * d + j] += p[j];
+        x->ss[k] += pp;
+        refresh(x, k, d);
         if (insert(t, ch, p, pp, tmp)) {
             auto ab = split(t, ch);
             int64_t n;
@@ -595,10 +593,6 @@ bool insert(ifgp_birch_s *t, BNode *x, const double *p, double pp, std::vector<d
             append(x, d, n, tmp.data(), ss, ab.second);
             return x->size() > t->B;
         }
-        x->n[k] += 1;
-        for (int j = 0; j < d; ++j) x->ls[(size_t)k * d + j] += p[j];
-        x->ss[k] += pp;
-        refresh(x, k, d);
         return false;
     }
     // leaf: absorb if the radius stays within the threshold
