@@ -378,3 +378,20 @@ def test_label_update_random_sweep(ifgp, i):
     log(f"label update sweep {i}: n={n} d={d} k={k} scale={scale} spread={spread:.3f} "
         f"threshold={thr:.4g} B={B} cuts={cuts}")
     _steps(ifgp, X, cuts, thr, B)
+
+
+def test_device_rows_fit_as_host_rows(ifgp):
+    """A partial fit from device rows (copied to the host, then inserted in
+    order) builds the tree a fit from the same rows in host memory builds,
+    bit for bit: 40,000 rows of width 64 in two partial fits."""
+    import torch
+    rng = np.random.default_rng(21)
+    c = rng.random((50, 64))
+    X = (c[rng.integers(0, 50, size=40_000)] + rng.normal(size=(40_000, 64)) * 0.05).astype(np.float32)
+    h = ifgp.Birch(64, 0.6, 30).partial_fit(X[:25_000]).partial_fit(X[25_000:])
+    Xt = torch.as_tensor(X, device="cuda")
+    g = ifgp.Birch(64, 0.6, 30).partial_fit(Xt[:25_000]).partial_fit(Xt[25_000:])
+    assert h.info() == g.info()
+    assert np.array_equal(h.centers(), g.centers())
+    h.destroy()
+    g.destroy()
