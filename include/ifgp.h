@@ -17,7 +17,7 @@
  *   layer    Z^(l) = ZNorm(tanh(phi * Z^(l-1))), ZNorm = column z-score
  *            (Eq. (4))
  *   output   Z~ = sigma(Z^(K)) (Eq. (4); Algorithm 1 up to the clustering
- *            step, which is not part of this library)
+ *            step, whose BIRCH calls follow at the end of this header)
  *
  * K is the number of hops (the paper's number of GNN layers L).
  *
@@ -227,10 +227,10 @@ IFGP_API ifgp_status ifgp_graph_info(ifgp_graph_t g, int64_t *N, int64_t *nnz,
                             int64_t *self_loops_dropped, int64_t *dups_dropped);
 
 /* The execution plan of the hop kernel: rows with at least 4096 neighbours
- * (one 256-thread block each, by default), rows with at least 256 (one wave
- * each, by default), the
- * number of thread blocks one hop launches, and the largest degree.  Any
- * output pointer may be NULL. */
+ * (one 256-thread block each, by default), rows with 128 to 4095 (one wave
+ * each, by default), the number of thread blocks one hop launches (BF16
+ * storage, width 64), and the largest degree.  Any output pointer may be
+ * NULL. */
 IFGP_API ifgp_status ifgp_plan_info(ifgp_graph_t g, int64_t *hub_rows, int64_t *medium_rows,
                                     int64_t *hop_blocks, int32_t *max_degree);
 
@@ -397,7 +397,7 @@ IFGP_API ifgp_status ifgp_birch_predict(ifgp_birch_t b, const float *Z, int64_t 
  * before each pass, whose size it reads back).
  * Z: device, n x d FP32, d <= 64; labels: device int32 n.  Errors as
  * ifgp_birch_predict, plus IFGP_E_INVALID for n >= 2^31.  A call that fails
- * part-way (IFGP_E_OOM, IFGP_E_HIP) leaves labels undefined and drops what
+ * part-way (IFGP_E_OOM, IFGP_E_DEVICE) leaves labels undefined and drops what
  * the tree kept for updates: the next call uploads every centroid again and
  * labels all of its rows in full.
  */
