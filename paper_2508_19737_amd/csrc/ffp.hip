@@ -161,6 +161,15 @@ __device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, 
     hi = (uint64_t)ah * bh + (t >> 32) + (u >> 32);
 }
 
+// a ^ b ^ c with one three-input bitwise instruction per 32-bit half (truth
+// table 0x96 is the odd-parity function of the three inputs)
+__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c) {
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32),
+                                                    (uint32_t)(c >> 32), 0x96);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64_t &c2,
                                               uint64_t &c3, uint64_t k0, uint64_t k1) {
     constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -174,7 +183,7 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64
         uint64_t hi0, lo0, hi1, lo1;
         mulhilo64(M0, c0, hi0, lo0);
         mulhilo64(M1, c2, hi1, lo1);
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        const uint64_t n0 = xor3(hi1, c1, k0), n2 = xor3(hi0, c3, k1);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
