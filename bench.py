@@ -352,7 +352,8 @@ def bench_serving(a, say):
     d in {32, 64}, tau=-1, K=8.  The Poisson rate is 0.7 x the measured
     capacity of the plain FP32 one-at-a-time path.  Batched BF16 continuous
     batching vs FP32 one-at-a-time on the same arrivals, plus a closed loop
-    (every request queued at t=0) for peak graphs/s."""
+    (every request queued at t=0) for peak graphs/s, with the edge lists in
+    pageable host memory and again in pinned host memory."""
     from paper_2508_19737_amd import serve
     from workloads.serving import graph_pool, request_stream
     say(f"serving: pool of {a.serve_pool} graphs, {a.serve_requests} requests")
@@ -361,10 +362,14 @@ def bench_serving(a, say):
                       cache_dir=os.path.join(ROOT, "build", "serving_pool"))
     say(f"serving: pool ready in {time.perf_counter() - t_gen:.1f} s")
 
-    def reqs(rate, storage, n):
-        return [serve.Request(rid=i, arrival=x["arrival"], src=x["graph"].src, dst=x["graph"].dst,
-                              N=x["graph"].N, tau=-1.0, K=8, d=x["d"], seed=x["seed"],
-                              storage=storage)
+    pinned = {}
+
+    def reqs(rate, storage, n, pin=False):
+        def edges(g):
+            return pinned[id(g)] if pin else (g.src, g.dst)
+        return [serve.Request(rid=i, arrival=x["arrival"], src=edges(x["graph"])[0],
+                              dst=edges(x["graph"])[1], N=x["graph"].N, tau=-1.0, K=8, d=x["d"],
+                              seed=x["seed"], storage=storage)
                 for i, x in enumerate(request_stream(pool, n, rate, seed=3))]
 
     n = a.serve_requests
@@ -380,10 +385,22 @@ def bench_serving(a, say):
     closed_b = serve.summarize(srv.run(reqs(float("inf"), "bf16", n), keep_outputs=False,
                                        progress=say))
     say(f"serving: closed loop batched {closed_b}")
+    # the same closed loop with every request's edge list in pinned host memory
+    # (as a server's receive buffers would be): the edge copies run at the
+    # DMA rate instead of through the runtime's pageable staging
+    import torch
+    for g in pool:
+        pinned[id(g)] = (torch.from_numpy(g.src).pin_memory(), torch.from_numpy(g.dst).pin_memory())
+    closed_b_pin = serve.summarize(srv.run(reqs(float("inf"), "bf16", n, pin=True),
+                                           keep_outputs=False, progress=say))
+    say(f"serving: closed loop batched, pinned edges {closed_b_pin}")
     srv.close()
     seq = serve.summarize(serve.sequential(reqs(rate, "f32", n), keep_outputs=False))
     say(f"serving: one at a time {seq}")
     closed_s = serve.summarize(serve.sequential(reqs(float("inf"), "f32", n), keep_outputs=False))
+    closed_s_pin = serve.summarize(serve.sequential(reqs(float("inf"), "f32", n, pin=True),
+                                                    keep_outputs=False))
+    pinned.clear()
     sizes = np.array([g.N for g in pool])
     used = np.array([g.N for g in {id(x["graph"]): x["graph"]
                                    for x in request_stream(pool, n, rate, seed=3)}.values()])
@@ -396,7 +413,9 @@ def bench_serving(a, say):
             "pool_nnz_total": int(sum(2 * g.num_edges for g in pool)),
             "rate_per_s": rate,
             "batched_bf16": batched, "one_at_a_time_fp32": seq,
-            "closed_loop_batched_bf16": closed_b, "closed_loop_one_at_a_time_fp32": closed_s}
+            "closed_loop_batched_bf16": closed_b, "closed_loop_one_at_a_time_fp32": closed_s,
+            "closed_loop_batched_bf16_pinned_edges": closed_b_pin,
+            "closed_loop_one_at_a_time_fp32_pinned_edges": closed_s_pin}
 
 
 def main():
