@@ -125,6 +125,29 @@ def test_out_of_range_ids_rejected(ifgp):
     assert e.value.status == -2
 
 
+@pytest.mark.parametrize("on_device", [False, True])
+@pytest.mark.parametrize("where,bad", [(0, 1000), (12_345, -1), (19_999, 1000)])
+def test_out_of_range_ids_rejected_large(ifgp, on_device, where, bad):
+    """Enough edges that the build's first radix pass makes the keys from the
+    edge lists itself: one id out of range anywhere still fails the build
+    with IFGP_E_RANGE, and a valid list of the same size builds."""
+    import torch
+    src, dst = random_edges(1000, 20_000, 5)
+    src, dst = src.copy(), dst.copy()
+    (dst if where % 2 else src)[where] = bad
+    if on_device:
+        src, dst = torch.as_tensor(src, device="cuda"), torch.as_tensor(dst, device="cuda")
+    with pytest.raises(ifgp.IfgpError) as e:
+        ifgp.Graph(src, dst, 1000)
+    assert e.value.status == -2
+    good_s, good_d = random_edges(1000, 20_000, 5)
+    g = ifgp.Graph(good_s, good_d, 1000)
+    rp, ci, _, _ = ffp.canonical_csr(good_s, good_d, 1000)
+    grp, gci, _ = g.export_csr()
+    assert np.array_equal(grp, rp) and np.array_equal(gci.astype(np.int64), ci)
+    g.destroy()
+
+
 # --------------------------------------------------------------------------- scales, noise
 @pytest.mark.parametrize("tau", [-1.0, -1.5, 0.0, 2.5, -80.0, -3.0])
 def test_scales_fp64(ifgp, config1, tau):
